@@ -1,0 +1,276 @@
+/*
+ * cbgmres.h -- C ABI of libcbgmres.so: restarted GMRES with a compressed
+ * Krylov basis (FRSZ2 block compression or low-precision casts) on one
+ * MI355X (gfx950) GPU.
+ *
+ * Method: GMRES with classical Gram-Schmidt and one conditional
+ * re-orthogonalisation, restarted every m steps (the paper's Fig. 1), whose
+ * basis vectors are stored compressed and decompressed inside the
+ * Gram-Schmidt projections and the solution update; everything else (SpMV,
+ * dot products, norms, Givens rotations, the solution) is FP64.  FRSZ2
+ * (Section III) groups 32 consecutive values under their largest biased IEEE
+ * exponent and keeps, per value, a sign bit and the leading l-1 bits of the
+ * significand aligned to that exponent (Eq. 2).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers are DEVICE pointers (memory on the current HIP device) unless
+ *    the name ends in _host.  The caller owns every buffer passed in; the
+ *    library never frees caller memory and never keeps a pointer past the
+ *    call (except the server, which copies its inputs).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Entry points documented as asynchronous only enqueue work on it.
+ *  - Return value: a cb_status.  Nothing is thrown across the ABI.  On an
+ *    error no kernel has been enqueued and cb_last_error() (thread-local)
+ *    describes the cause.
+ *  - Sizes n are row counts (1 <= n < 2^31 - 32); indices are 32-bit.
+ */
+#ifndef CBGMRES_H
+#define CBGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cb_status {
+    CB_OK = 0,
+    CB_ERR_INVALID_ARG = 1,      /* null pointer, bad size, bad format ... */
+    CB_ERR_UNSUPPORTED_BITS = 2, /* FRSZ2 bit width other than 16, 21, 32 */
+    CB_ERR_NONFINITE = 3,        /* Inf/NaN met in a solve */
+    CB_ERR_NOT_CONVERGED = 4,    /* iteration or cycle cap reached */
+    CB_ERR_WORKSPACE = 5,        /* workspace too small */
+    CB_ERR_OVER_BUDGET = 6,      /* server request larger than the HBM budget */
+    CB_ERR_HIP = 7,              /* a HIP runtime call failed */
+    CB_PENDING = 8,              /* server ticket not finished yet */
+    CB_ERR_NOT_FOUND = 9         /* unknown server ticket */
+} cb_status;
+
+/* Basis storage formats.  float16 is IEEE binary16 rounded to nearest-even
+ * in one step from float64; float32 likewise.  frsz2_l is FRSZ2 with block
+ * size 32 and l bits per value. */
+typedef enum cb_basis_format {
+    CB_F64 = 0,
+    CB_F32 = 1,
+    CB_F16 = 2,
+    CB_FRSZ2_16 = 3,
+    CB_FRSZ2_21 = 4,
+    CB_FRSZ2_32 = 5
+} cb_basis_format;
+
+const char* cb_status_string(int status);
+const char* cb_last_error(void);
+
+/* ======================================================================
+ * FRSZ2 codec (Section III-A compression steps 1-6, Section III-B
+ * decompression steps 1-4, storage layout of Eq. 3).
+ *
+ * Layout of a compressed vector of n values, nb = ceil(n/32) blocks:
+ *   exps[nb]     uint32: the block's largest biased IEEE exponent field E
+ *                (0..2047; the value grid is 2^(max(E,1)-1023-(l-2)));
+ *   words[l*nb]  uint32: block b owns words [b*l, (b+1)*l), holding the
+ *                32 l-bit codes of the block as one little-endian bit stream,
+ *                code q at bits [q*l, (q+1)*l); a code is sign << (l-1) |
+ *                floor(|x| / grid), i.e. the significand truncated to l-1
+ *                bits after alignment to E.
+ * The exponent and value arrays are separate (Section III-C, item 5).
+ * A partial last block is encoded as if padded with +0.0.
+ * ====================================================================== */
+
+/* ceil(n/32) */
+int64_t frsz2_exponent_words(int64_t n);
+/* bits * ceil(n/32), or -1 for an unsupported width */
+int64_t frsz2_value_words(int64_t n, int bits);
+
+/* Compress x[n] (float64) into exps/words.  bits in {16, 21, 32}.
+ * nonfinite_flag (nullable, device int32) is set to 1 -- never cleared -- when
+ * a block holds Inf or NaN; that block's words are then unspecified.
+ * Asynchronous. */
+int frsz2_compress(const double* x, int64_t n, int bits, uint32_t* exps, uint32_t* words,
+                   int32_t* nonfinite_flag, void* stream);
+
+/* Decompress n values into x[n] (float64).  Every code decodes exactly (the
+ * values are multiples of 2^-1074 below 2^1024).  Asynchronous. */
+int frsz2_decompress(const uint32_t* exps, const uint32_t* words, int64_t n, int bits,
+                     double* x, void* stream);
+
+/* ======================================================================
+ * Compressed basis V = [v_0 .. v_{ncols-1}] (Fig. 1, the highlighted
+ * storage sites) and the fused hot-path primitives.
+ *
+ * Column c of `values` starts at byte c * cb_basis_column_bytes(format, n);
+ * frsz2 columns keep their exponents at exps + c * cb_basis_exponent_words.
+ * Rows n .. 32*ceil(n/32)-1 of every column are stored as +0.0.  Float
+ * columns are float64/float32/binary16 arrays of 32*ceil(n/32) entries; frsz2
+ * columns are the `words` array above.  `exps` is ignored (may be NULL) for
+ * float formats.
+ * ====================================================================== */
+typedef struct cb_basis {
+    int32_t format;   /* cb_basis_format */
+    int32_t n;        /* rows */
+    int32_t ncols;    /* capacity in columns */
+    int32_t reserved; /* 0 */
+    void* values;     /* device */
+    uint32_t* exps;   /* device, frsz2 only */
+} cb_basis;
+
+int64_t cb_basis_column_bytes(int format, int64_t n);
+int64_t cb_basis_exponent_words(int format, int64_t n); /* 0 for float formats */
+
+/* Normalise and store one basis column (Fig. 1 steps 1, 13-14):
+ * v = w / *divisor with IEEE division per entry (divisor: device double;
+ * NULL stores w unchanged); column `col` := Q(v); if v_out is non-NULL it
+ * receives the float64 v (n entries).  w and v_out may alias.
+ * nonfinite_flag as for frsz2_compress.  Asynchronous. */
+int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double* divisor,
+                   double* v_out, int32_t* nonfinite_flag, void* stream);
+
+/* x[n] := D(column col), float64.  Asynchronous. */
+int cb_basis_load(const cb_basis* V, int32_t col, double* x, void* stream);
+
+/* Bytes of reduction workspace needed by the primitives below for n rows and
+ * up to ncols columns (per-workgroup partial sums). */
+int64_t cb_reduce_workspace_bytes(int32_t n, int32_t ncols);
+
+/* Classical Gram-Schmidt projection with decompression fused into the read
+ * (Fig. 1 step 5, first half): h[i] = sum_k D(v_i)[k] * w[k] for
+ * i = 0..j-1, all against the same w.  h: device float64[j].  The sum over k
+ * runs in a fixed order that depends on n only (deterministic).
+ * Asynchronous. */
+int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, void* work,
+                   size_t work_bytes, void* stream);
+
+/* Classical Gram-Schmidt update with decompression fused in (Fig. 1 step 5,
+ * second half, and step 6): w[k] -= sum_{i<j} h[i] * D(v_i)[k] (each row's
+ * correction summed over i in order, then subtracted), and, if norm2 is
+ * non-NULL, *norm2 = ||w||^2 after the update (device double).
+ * Asynchronous. */
+int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, double* norm2,
+                    void* work, size_t work_bytes, void* stream);
+
+/* Solution update with decompression fused in (Fig. 1 step 17):
+ * x[k] += sum_{i<j} y[i] * D(v_i)[k].  y: device float64[j].  Asynchronous. */
+int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream);
+
+/* ======================================================================
+ * Sparse matrix (CSR, int32 indices sorted within rows, float64 values).
+ * ====================================================================== */
+typedef struct cb_csr {
+    int32_t n;   /* rows = columns */
+    int32_t nnz;
+    const int32_t* row_ptr; /* device, n+1 */
+    const int32_t* col;     /* device, nnz */
+    const double* val;      /* device, nnz */
+} cb_csr;
+
+/* y = A x (Fig. 1 step 3, M = I) and, if norm2 != NULL, *norm2 = ||y||^2
+ * (step 4).  Asynchronous. */
+int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
+            size_t work_bytes, void* stream);
+
+/* r = b - A x and, if norm2 != NULL, *norm2 = ||r||^2 (Fig. 1 step 1).
+ * Asynchronous. */
+int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, double* norm2,
+                void* work, size_t work_bytes, void* stream);
+
+/* ======================================================================
+ * Solver (Fig. 1; stopping rule Eq. 4).
+ * ====================================================================== */
+typedef struct cb_options {
+    double eta;                /* re-orthogonalisation threshold (Fig. 1 step 7); <= 0: 1/sqrt(2) */
+    int32_t max_iters;         /* cap on Arnoldi steps; <= 0: 20000 */
+    int32_t max_cycles;        /* cap on restart cycles; 0 = none.  When it is hit the
+                                  solve returns after the x update without a final
+                                  explicit residual (status CB_ERR_NOT_CONVERGED) */
+    int32_t literal_breakdown; /* 1: step 12 compares h_{j+1,j} with eta * omega as
+                                  printed; 0 (default): with eta times the norm before
+                                  the re-orthogonalisation pass */
+    int32_t reserved;
+} cb_options;
+
+typedef struct cb_result {
+    int32_t iterations;          /* Arnoldi steps (SpMVs inside cycles) */
+    int32_t restarts;            /* cycles run */
+    int32_t reorths;             /* steps that ran the second Gram-Schmidt pass */
+    int32_t breakdowns;          /* cycles ended by the breakdown test */
+    int32_t converged;           /* 1 iff the explicit residual met tol */
+    int32_t status;              /* cb_status of the solve */
+    double rel_residual;         /* last explicit ||b - A x|| / ||b||; -1 if not evaluated */
+    double implicit_rel_residual;/* last |g_{j+1}| / ||b|| */
+    double seconds;              /* wall time of the solve */
+    double basis_bytes;          /* algorithmic bytes read+written in the basis kernels */
+} cb_result;
+
+/* Device workspace bytes cbgmres_solve needs for n rows, restart m, format. */
+int64_t cbgmres_workspace_bytes(int32_t n, int32_t m, int format);
+
+/* Solve A x = b.  x holds x0 on entry and the iterate on return (device,
+ * float64[n]).  m >= 1 is the restart length, tol > 0 the relative residual
+ * ||b - A x|| <= tol ||b|| that ends the solve (checked on the explicit
+ * residual at a restart, Eq. 4; the implicit residual only ends a cycle
+ * early).  workspace may be NULL (the library allocates and frees it) or a
+ * device buffer of at least cbgmres_workspace_bytes.  history_host (nullable)
+ * receives up to history_cap implicit relative residuals, one per step.
+ * result_host receives the statistics.  Synchronous: returns when the solve
+ * is done.  b = 0 gives x = 0 after 0 iterations.  A cap reached returns
+ * CB_ERR_NOT_CONVERGED with x the last iterate; Inf/NaN returns
+ * CB_ERR_NONFINITE. */
+int cbgmres_solve(const cb_csr* A, const double* b, double* x, int32_t m, double tol, int format,
+                  const cb_options* opt, void* workspace, size_t workspace_bytes,
+                  double* history_host, int64_t history_cap, cb_result* result_host, void* stream);
+
+/* Mixed-precision form: FP64 iterative refinement around an inner
+ * compressed-basis GMRES.  Each outer step computes r = b - A x in FP64,
+ * runs one inner cycle of GMRES(m) on A d = r from d = 0 with the given basis
+ * format and relative tolerance inner_tol, and adds x += d in FP64; it stops
+ * when ||b - A x|| <= tol ||b|| or after max_outer steps.  Synchronous.
+ * result_host: iterations = inner steps in total, restarts = outer steps. */
+int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, double inner_tol,
+                     double tol, int format, int32_t max_outer, cb_result* result_host,
+                     void* stream);
+
+/* ======================================================================
+ * Serving: continuous batching of solve requests on one GPU.
+ * Requests are admitted while their device footprint fits in the HBM budget
+ * (basis n*(m+1) stored bytes + CSR + work vectors); later arrivals wait in
+ * FIFO order and are admitted as earlier solves finish and release memory.
+ * Admitted solves run concurrently on a pool of HIP streams.  Each solve runs
+ * the same kernels with the same reduction order as cbgmres_solve, so its
+ * result does not depend on what else runs beside it.
+ * ====================================================================== */
+typedef struct cb_server cb_server;
+
+/* Create a server on `device` with an HBM budget in bytes and `lanes`
+ * concurrent solve lanes (streams).  NULL on failure (cb_last_error). */
+cb_server* cb_server_create(size_t hbm_budget_bytes, int device, int lanes);
+
+/* Bytes a request of this shape is charged against the budget. */
+int64_t cb_server_request_bytes(int32_t n, int32_t nnz, int32_t m, int format);
+
+/* Submit a solve.  Inputs are HOST arrays, copied before return.  Returns
+ * CB_ERR_OVER_BUDGET if the request alone exceeds the budget.  Non-blocking;
+ * *ticket identifies the request. */
+int cb_server_submit(cb_server* s, int32_t n, int32_t nnz, const int32_t* row_ptr_host,
+                     const int32_t* col_host, const double* val_host, const double* b_host,
+                     const double* x0_host /* nullable: zeros */, int32_t m, double tol,
+                     int format, uint64_t* ticket);
+
+/* CB_PENDING until the ticket's solve has finished; then copies the solution
+ * into x_host (nullable), the statistics into result_host (nullable), the
+ * submit/start/finish times in seconds since server creation into
+ * times_host[3] (nullable) and releases the ticket. */
+int cb_server_poll(cb_server* s, uint64_t ticket, double* x_host, cb_result* result_host,
+                   double* times_host);
+
+/* Bytes currently charged against the budget, and requests waiting. */
+int cb_server_stats(cb_server* s, int64_t* charged_bytes, int32_t* queued, int32_t* running);
+
+/* Wait for every submitted solve, then free the server. */
+void cb_server_destroy(cb_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBGMRES_H */

@@ -1,0 +1,228 @@
+// C ABI: argument checks and launches for the codec, basis and SpMV entry
+// points, plus the thread-local error text.
+#include <cstdarg>
+#include <cstring>
+
+#include "cb_internal.hpp"
+
+namespace cb {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int fail(int status, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int64_t column_bytes(int f, int64_t n) {
+    const int64_t nb = nblocks(n);
+    switch (f) {
+    case CB_F64: return nb * 32 * 8;
+    case CB_F32: return nb * 32 * 4;
+    case CB_F16: return nb * 32 * 2;
+    case CB_FRSZ2_16:
+    case CB_FRSZ2_21:
+    case CB_FRSZ2_32: return nb * frsz2_bits_of(f) * 4;
+    default: return -1;
+    }
+}
+
+int64_t exponent_words(int f, int64_t n) { return frsz2_bits_of(f) ? nblocks(n) : 0; }
+
+int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz) {
+    int64_t a = (int64_t)row_groups(n) * (ncols > 0 ? ncols : 1);
+    int64_t b = nnz > 0 ? spmv_groups(n, nnz) : 0;
+    return 8 * (a > b ? a : b);
+}
+
+static bool bad_n(int64_t n) { return n < 1 || n > (int64_t)INT32_MAX - 64; }
+
+static int check_basis(const cb_basis* V, int need_cols) {
+    if (!V) return fail(CB_ERR_INVALID_ARG, "basis descriptor is NULL");
+    if (!valid_format(V->format)) return fail(CB_ERR_INVALID_ARG, "unknown basis format %d", V->format);
+    if (bad_n(V->n)) return fail(CB_ERR_INVALID_ARG, "basis rows n=%d out of range", V->n);
+    if (V->ncols < need_cols) return fail(CB_ERR_INVALID_ARG, "basis has %d columns, %d needed", V->ncols, need_cols);
+    if (!V->values) return fail(CB_ERR_INVALID_ARG, "basis values pointer is NULL");
+    if (frsz2_bits_of(V->format) && !V->exps) return fail(CB_ERR_INVALID_ARG, "frsz2 basis needs exps");
+    return CB_OK;
+}
+
+}  // namespace cb
+
+using namespace cb;
+
+extern "C" {
+
+const char* cb_status_string(int status) {
+    switch (status) {
+    case CB_OK: return "ok";
+    case CB_ERR_INVALID_ARG: return "invalid argument";
+    case CB_ERR_UNSUPPORTED_BITS: return "unsupported FRSZ2 bit width";
+    case CB_ERR_NONFINITE: return "non-finite value";
+    case CB_ERR_NOT_CONVERGED: return "not converged";
+    case CB_ERR_WORKSPACE: return "workspace too small";
+    case CB_ERR_OVER_BUDGET: return "request exceeds the HBM budget";
+    case CB_ERR_HIP: return "HIP runtime error";
+    case CB_PENDING: return "pending";
+    case CB_ERR_NOT_FOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char* cb_last_error(void) { return g_err; }
+
+int64_t frsz2_exponent_words(int64_t n) { return n < 0 ? -1 : nblocks(n); }
+
+int64_t frsz2_value_words(int64_t n, int bits) {
+    if (n < 0 || (bits != 16 && bits != 21 && bits != 32)) return -1;
+    return (int64_t)bits * nblocks(n);
+}
+
+static int format_of_bits(int bits) {
+    return bits == 16 ? CB_FRSZ2_16 : bits == 21 ? CB_FRSZ2_21 : bits == 32 ? CB_FRSZ2_32 : -1;
+}
+
+int frsz2_compress(const double* x, int64_t n, int bits, uint32_t* exps, uint32_t* words,
+                   int32_t* nonfinite_flag, void* stream) {
+    const int f = format_of_bits(bits);
+    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (16, 21 or 32)", bits);
+    if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
+    cb_basis V{f, (int32_t)n, 1, 0, words, exps};
+    int32_t* flag = nonfinite_flag;
+    launch_store(f, V, 0, x, nullptr, nullptr, flag, nullptr, (hipStream_t)stream);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int frsz2_decompress(const uint32_t* exps, const uint32_t* words, int64_t n, int bits, double* x,
+                     void* stream) {
+    const int f = format_of_bits(bits);
+    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (16, 21 or 32)", bits);
+    if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
+    cb_basis V{f, (int32_t)n, 1, 0, const_cast<uint32_t*>(words), const_cast<uint32_t*>(exps)};
+    launch_load(f, V, 0, x, (hipStream_t)stream);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int64_t cb_basis_column_bytes(int format, int64_t n) {
+    if (!valid_format(format) || n < 0) return -1;
+    return column_bytes(format, n);
+}
+
+int64_t cb_basis_exponent_words(int format, int64_t n) {
+    if (!valid_format(format) || n < 0) return -1;
+    return exponent_words(format, n);
+}
+
+int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double* divisor,
+                   double* v_out, int32_t* nonfinite_flag, void* stream) {
+    if (int st = check_basis(V, col + 1)) return st;
+    if (col < 0 || !w) return fail(CB_ERR_INVALID_ARG, "bad column or NULL w");
+    launch_store(V->format, *V, col, w, divisor, v_out, nonfinite_flag, nullptr, (hipStream_t)stream);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int cb_basis_load(const cb_basis* V, int32_t col, double* x, void* stream) {
+    if (int st = check_basis(V, col + 1)) return st;
+    if (col < 0 || !x) return fail(CB_ERR_INVALID_ARG, "bad column or NULL x");
+    launch_load(V->format, *V, col, x, (hipStream_t)stream);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int64_t cb_reduce_workspace_bytes(int32_t n, int32_t ncols) {
+    if (bad_n(n) || ncols < 0) return -1;
+    return reduce_workspace_bytes(n, ncols, 0);
+}
+
+int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, void* work,
+                   size_t work_bytes, void* stream) {
+    if (int st = check_basis(V, j)) return st;
+    if (j < 1 || !w || !h || !work) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if ((int64_t)work_bytes < reduce_workspace_bytes(V->n, j, 0))
+        return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", work_bytes,
+                    (long long)reduce_workspace_bytes(V->n, j, 0));
+    hipStream_t s = (hipStream_t)stream;
+    double* part = static_cast<double*>(work);
+    launch_project(V->format, *V, j, w, part, nullptr, s);
+    launch_reduce(part, row_groups(V->n), j, h, 0, nullptr, s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, double* norm2,
+                    void* work, size_t work_bytes, void* stream) {
+    if (int st = check_basis(V, j)) return st;
+    if (j < 1 || !w || !h) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (norm2 && (!work || (int64_t)work_bytes < reduce_workspace_bytes(V->n, 1, 0)))
+        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes",
+                    (long long)reduce_workspace_bytes(V->n, 1, 0));
+    hipStream_t s = (hipStream_t)stream;
+    double* part = norm2 ? static_cast<double*>(work) : nullptr;
+    launch_subtract(V->format, *V, j, nullptr, h, w, part, nullptr, -1, s);
+    if (norm2) launch_reduce(part, row_groups(V->n), 1, norm2, 0, nullptr, s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream) {
+    if (int st = check_basis(V, j)) return st;
+    if (j < 1 || !y || !x) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    launch_subtract(V->format, *V, j, nullptr, y, x, nullptr, nullptr, +1, (hipStream_t)stream);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+static int check_csr(const cb_csr* A) {
+    if (!A) return fail(CB_ERR_INVALID_ARG, "matrix descriptor is NULL");
+    if (bad_n(A->n) || A->nnz < 0) return fail(CB_ERR_INVALID_ARG, "bad matrix size n=%d nnz=%d", A->n, A->nnz);
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val)))
+        return fail(CB_ERR_INVALID_ARG, "NULL matrix array");
+    return CB_OK;
+}
+
+int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
+            size_t work_bytes, void* stream) {
+    if (int st = check_csr(A)) return st;
+    if (!x || !y) return fail(CB_ERR_INVALID_ARG, "NULL vector");
+    const int G = spmv_groups(A->n, A->nnz);
+    if (norm2 && (!work || work_bytes < (size_t)G * 8))
+        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)G * 8);
+    hipStream_t s = (hipStream_t)stream;
+    double* part = norm2 ? static_cast<double*>(work) : nullptr;
+    launch_spmv(*A, x, nullptr, y, part, 0, nullptr, s);
+    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, double* norm2,
+                void* work, size_t work_bytes, void* stream) {
+    if (int st = check_csr(A)) return st;
+    if (!x || !r || !b) return fail(CB_ERR_INVALID_ARG, "NULL vector");
+    const int G = spmv_groups(A->n, A->nnz);
+    if (norm2 && (!work || work_bytes < (size_t)G * 8))
+        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)G * 8);
+    hipStream_t s = (hipStream_t)stream;
+    double* part = norm2 ? static_cast<double*>(work) : nullptr;
+    launch_spmv(*A, x, b, r, part, 1, nullptr, s);
+    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/cbgmres.h"
+
+namespace cb {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int fail(int status, const char* fmt, ...);
+
+#define CB_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::cb::fail(CB_ERR_HIP, "%s failed: %s (%s:%d)", #call,                 \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                 \
+    } while (0)
+
+// ---------------------------------------------------------------- geometry
+constexpr int kBS = 32;           // FRSZ2 block size (values per shared exponent)
+constexpr int kSeg = 8;           // rows per thread in the row-segment kernels
+constexpr int kThreads = 256;     // threads per workgroup in the row kernels
+constexpr int kRowsPerWG = kThreads * kSeg;  // 2048 rows = 64 FRSZ2 blocks
+constexpr int kColChunk = 64;     // basis columns per workgroup (grid.y tiles more)
+
+inline int64_t nblocks(int64_t n) { return (n + kBS - 1) / kBS; }
+inline int64_t padded_rows(int64_t n) { return nblocks(n) * kBS; }
+inline int row_groups(int64_t n) { return (int)((padded_rows(n) + kRowsPerWG - 1) / kRowsPerWG); }
+
+inline bool valid_format(int f) { return f >= CB_F64 && f <= CB_FRSZ2_32; }
+inline int frsz2_bits_of(int f) {
+    return f == CB_FRSZ2_16 ? 16 : f == CB_FRSZ2_21 ? 21 : f == CB_FRSZ2_32 ? 32 : 0;
+}
+int64_t column_bytes(int f, int64_t n);
+int64_t exponent_words(int f, int64_t n);
+
+// Device view of a basis (column-major, see cbgmres.h).
+struct BasisView {
+    const unsigned char* values;
+    const uint32_t* exps;
+    int64_t col_bytes;
+    int64_t exp_stride;  // exponent words per column
+    int32_t n;
+    int32_t np;          // 32 * ceil(n/32)
+};
+inline BasisView view_of(const cb_basis& V) {
+    BasisView b;
+    b.values = static_cast<const unsigned char*>(V.values);
+    b.exps = V.exps;
+    b.col_bytes = column_bytes(V.format, V.n);
+    b.exp_stride = exponent_words(V.format, V.n);
+    b.n = V.n;
+    b.np = (int32_t)padded_rows(V.n);
+    return b;
+}
+
+// SpMV geometry: lanes per row and rows per workgroup depend on the matrix only.
+int spmv_lanes_per_row(int32_t n, int32_t nnz);
+int spmv_groups(int32_t n, int32_t nnz);
+int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz);
+
+// ---------------------------------------------------------------- launchers (no validation)
+// `guard` (nullable device int): a kernel whose guard reads 0 does nothing.
+// `jdev` (nullable device int): column count read on the device (overrides j).
+void launch_store(int fmt, const cb_basis& V, int col, const double* w, const double* divisor,
+                  double* v_out, int32_t* flag, const int* guard, hipStream_t s);
+void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s);
+// Stage 1 of h = V^T w: partials[c * G + g] for c < j.
+void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* partials,
+                    const int* guard, hipStream_t s);
+// w -= V h (h device), norm partials[g] (nullable).
+void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const double* h,
+                     double* w, double* partials, const int* guard, int accumulate_sign,
+                     hipStream_t s);
+// Stage 2: out[c] (op 0: =, op 1: +=) = sum_g partials[c * G + g], c < ncols.
+void launch_reduce(const double* partials, int G, int ncols, double* out, int op,
+                   const int* guard, hipStream_t s);
+// y = A x (mode 0) or y = b - A x (mode 1); norm partials (nullable).
+void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
+                 int mode, const int* guard, hipStream_t s);
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+
+}  // namespace cb

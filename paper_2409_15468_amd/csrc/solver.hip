@@ -1,0 +1,502 @@
+// Restarted GMRES with a compressed basis (the paper's Fig. 1) driven from
+// the host with device-resident control.
+//
+// Every scalar decision of the method -- the re-orthogonalisation test (step
+// 7), breakdown (step 12), the Givens rotations and the implicit residual
+// (steps 16-17), the end of a cycle -- is taken on the GPU by one-wave kernels
+// that write a control block in device memory.  The host enqueues a whole
+// cycle of m steps without waiting; kernels of steps after the cycle has ended
+// read the control block and return at once.  The host waits once per cycle,
+// after the explicit residual of the restart (step 1 / 18, Eq. 4) has been
+// evaluated, to learn whether to stop.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cb_internal.hpp"
+#include "reduce.hpp"
+
+namespace cb {
+
+using namespace dev;
+
+struct State {
+    double nb, tol_abs, eta;
+    double beta;       // ||r|| at the start of the cycle
+    double r2;         // reduction target: ||r||^2 (or ||b||^2 at init)
+    double om2;        // ||A v||^2
+    double hn2;        // ||w||^2 after a Gram-Schmidt pass
+    double hn;         // h_{j+1,j}: the divisor of the next basis vector
+    double omega;      // ||A v||
+    double omega_pre;  // ||w|| before the re-orthogonalisation pass
+    double gabs;       // |g_{j+1}|
+    double rel;        // last explicit relative residual
+    double basis_bytes;
+    int32_t active;    // 1 while the current cycle continues
+    int32_t reorth;    // 1 while the current step needs the second pass
+    int32_t steps;     // steps taken in the current cycle
+    int32_t prev_steps;
+    int32_t iters, reorths, breakdowns, converged;
+    int32_t stop, status, cycles, max_iters;
+    int32_t literal, pad0, pad1, pad2;
+};
+
+struct Layout {
+    int64_t state, flag, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, total;
+};
+
+static int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+static Layout layout_of(int32_t n, int32_t m, int fmt) {
+    Layout L;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { int64_t o = off; off += al(bytes); return o; };
+    L.state = take(sizeof(State));
+    L.flag = take(sizeof(int32_t));
+    L.H = take((int64_t)(m + 1) * m * 8);
+    L.cs = take((int64_t)m * 8);
+    L.sn = take((int64_t)m * 8);
+    L.g = take((int64_t)(m + 1) * 8);
+    L.u = take((int64_t)(m + 1) * 8);
+    L.y = take((int64_t)m * 8);
+    L.hist = take((int64_t)m * 8);
+    L.w = take(padded_rows(n) * 8);
+    L.v = take(padded_rows(n) * 8);
+    L.vals = take(column_bytes(fmt, n) * (m + 1));
+    L.exps = take(exponent_words(fmt, n) * 4 * (m + 1));
+    // partial sums: the basis kernels' groups times columns, or one per SpMV
+    // workgroup (at least 4 rows each)
+    int64_t pb = (int64_t)row_groups(n) * (m + 1);
+    int64_t ps = (int64_t)n / 4 + 1;
+    L.part = take(8 * (pb > ps ? pb : ps));
+    L.total = off;
+    return L;
+}
+
+// ----------------------------------------------------------------- scalar kernels
+__global__ void k_sumsq(const double* __restrict__ x, int n, double* __restrict__ partials) {
+    int row0 = blockIdx.x * kRowsPerWG + threadIdx.x * kSeg;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q)
+        if (row0 + q < n) s = fma(x[row0 + q], x[row0 + q], s);
+    s = block_sum<kThreads>(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_init(State* st, int32_t* flag, double tol, double eta, int max_iters, int literal) {
+    if (threadIdx.x != 0) return;
+    State z = {};
+    z.nb = sqrt(st->r2);
+    z.tol_abs = tol * z.nb;
+    z.eta = eta;
+    z.max_iters = max_iters;
+    z.literal = literal;
+    z.rel = -1.0;
+    z.gabs = -1.0;
+    if (z.nb == 0.0) {
+        z.stop = 1;
+        z.converged = 1;
+        z.rel = 0.0;
+        z.gabs = 0.0;
+    } else if (!isfinite(z.nb)) {
+        z.stop = 1;
+        z.status = CB_ERR_NONFINITE;
+    }
+    *st = z;
+    *flag = 0;
+}
+
+// Step 1 / 18: beta = ||b - A x|| and the stop test of Eq. 4.
+__global__ void k_cycle_begin(State* st, const int32_t* flag, double* g, int m) {
+    const int t = threadIdx.x;
+    __shared__ int go;
+    if (t == 0) {
+        State& s = *st;
+        s.prev_steps = s.steps;
+        s.steps = 0;
+        s.active = 0;
+        s.reorth = 0;
+        s.beta = sqrt(s.r2);
+        s.rel = s.beta / s.nb;
+        go = 0;
+        if (!isfinite(s.beta) || *flag) {
+            s.stop = 1;
+            s.status = CB_ERR_NONFINITE;
+        } else if (s.beta <= s.tol_abs) {
+            s.stop = 1;
+            s.converged = 1;
+        } else if (s.iters >= s.max_iters) {
+            s.stop = 1;
+            s.status = CB_ERR_NOT_CONVERGED;
+        } else {
+            s.active = 1;
+            s.cycles += 1;
+            go = 1;
+        }
+    }
+    __syncthreads();
+    if (go)
+        for (int i = t; i <= m; i += blockDim.x) g[i] = i == 0 ? st->beta : 0.0;
+}
+
+// Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
+// Givens rotations, implicit residual, end-of-cycle decision.
+__device__ void finish_step(State& s, double* H, double* cs, double* sn, double* g,
+                            double* hist, int j, int m, int breakdown) {
+    double hn = s.hn;
+    if (!isfinite(hn)) {
+        s.active = 0;
+        s.stop = 1;
+        s.status = CB_ERR_NONFINITE;
+        return;
+    }
+    if (hn == 0.0) breakdown = 1;
+    double* h = H + (int64_t)j * (m + 1);
+    h[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        double a = h[i], b = h[i + 1];
+        h[i] = cs[i] * a + sn[i] * b;
+        h[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    double rho = sqrt(h[j] * h[j] + hn * hn);
+    cs[j] = h[j] / rho;
+    sn[j] = hn / rho;
+    h[j] = rho;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    s.iters += 1;
+    s.steps = j + 1;
+    s.gabs = fabs(g[j + 1]);
+    hist[j] = s.gabs;
+    if (s.gabs <= s.tol_abs || breakdown || s.iters >= s.max_iters || j + 1 == m) {
+        s.active = 0;
+        s.breakdowns += breakdown;
+    }
+}
+
+// After the first Gram-Schmidt pass: omega, h_{j+1,j} and the step 7 test.
+__global__ void k_step_check(State* st, double* H, double* cs, double* sn, double* g,
+                             double* hist, int j, int m, double col_bytes) {
+    if (threadIdx.x != 0) return;
+    State& s = *st;
+    if (!s.active) return;
+    s.omega = sqrt(s.om2);
+    s.hn = sqrt(s.hn2);
+    s.basis_bytes += 2.0 * (j + 1) * col_bytes;
+    if (s.hn < s.eta * s.omega) {
+        s.reorth = 1;
+        s.omega_pre = s.hn;
+    } else {
+        s.reorth = 0;
+        finish_step(s, H, cs, sn, g, hist, j, m, 0);
+    }
+}
+
+// After the re-orthogonalisation pass (steps 8-11): h += u, new norm, breakdown.
+__global__ void k_step_finish(State* st, double* H, const double* u, double* cs, double* sn,
+                              double* g, double* hist, int j, int m, double col_bytes) {
+    State& s = *st;
+    if (!s.active || !s.reorth) return;
+    double* h = H + (int64_t)j * (m + 1);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] += u[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    s.hn = sqrt(s.hn2);
+    s.reorths += 1;
+    s.basis_bytes += 2.0 * (j + 1) * col_bytes;
+    int bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
+    s.reorth = 0;
+    finish_step(s, H, cs, sn, g, hist, j, m, bd);
+}
+
+// Step 17: back-substitution R y = g over the cycle's steps.
+__global__ void k_backsolve(State* st, const double* H, const double* g, double* y, int m,
+                            double col_bytes) {
+    if (threadIdx.x != 0) return;
+    const int k1 = st->steps;
+    for (int i = k1 - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int k = i + 1; k < k1; ++k) s -= H[(int64_t)k * (m + 1) + i] * y[k];
+        y[i] = s / H[(int64_t)i * (m + 1) + i];
+    }
+    st->basis_bytes += (double)k1 * col_bytes;
+}
+
+__global__ void k_axpy(double* __restrict__ x, const double* __restrict__ d, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] + d[i];
+}
+
+// ----------------------------------------------------------------- host side
+struct Pinned {
+    void* p = nullptr;
+    size_t cap = 0;
+    void* get(size_t bytes) {
+        if (bytes > cap) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+            if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+            cap = bytes;
+        }
+        return p;
+    }
+};
+static thread_local Pinned g_pinned;
+
+struct Ws {
+    unsigned char* base;
+    Layout L;
+    template <class T>
+    T* at(int64_t off) const { return reinterpret_cast<T*>(base + off); }
+};
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ||x||^2 of a device vector into *dst (device), using the partial buffer.
+static void enqueue_sumsq(const double* x, int n, double* part, double* dst, hipStream_t s) {
+    const int G = row_groups(n);
+    k_sumsq<<<G, kThreads, 0, s>>>(x, n, part);
+    launch_reduce(part, G, 1, dst, 0, nullptr, s);
+}
+
+// The solve proper, on a prepared workspace.  Returns a cb_status.
+static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double tol, int fmt,
+                      const cb_options* opt, const Ws& W, double* history_host,
+                      int64_t history_cap, cb_result* res, hipStream_t s) {
+    const double t0 = now_s();
+    const int n = A.n;
+    const double eta = (opt && opt->eta > 0) ? opt->eta : 0.7071067811865476;
+    const int max_iters = (opt && opt->max_iters > 0) ? opt->max_iters : 20000;
+    const int max_cycles = opt ? opt->max_cycles : 0;
+    const int literal = opt ? opt->literal_breakdown : 0;
+
+    State* st = W.at<State>(W.L.state);
+    int32_t* flag = W.at<int32_t>(W.L.flag);
+    double* H = W.at<double>(W.L.H);
+    double* cs = W.at<double>(W.L.cs);
+    double* sn = W.at<double>(W.L.sn);
+    double* g = W.at<double>(W.L.g);
+    double* u = W.at<double>(W.L.u);
+    double* y = W.at<double>(W.L.y);
+    double* hist = W.at<double>(W.L.hist);
+    double* w = W.at<double>(W.L.w);
+    double* v = W.at<double>(W.L.v);
+    double* part = W.at<double>(W.L.part);
+    cb_basis V{fmt, n, m + 1, 0, W.base + W.L.vals,
+               frsz2_bits_of(fmt) ? W.at<uint32_t>(W.L.exps) : nullptr};
+    const double cbytes = (double)column_bytes(fmt, n);
+    const int Gb = row_groups(n);
+    const int Gs = spmv_groups(n, A.nnz);
+    int* active = &st->active;
+    int* reorth = &st->reorth;
+    int* steps = &st->steps;
+
+    State* hs = static_cast<State*>(g_pinned.get(sizeof(State) + (size_t)m * 8));
+    if (!hs) return fail(CB_ERR_HIP, "hipHostMalloc failed");
+    double* hh = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(hs) + sizeof(State));
+    int64_t recorded = 0;
+
+    // ||b||, tolerances, counters
+    enqueue_sumsq(b, n, part, &st->r2, s);
+    k_init<<<1, 64, 0, s>>>(st, flag, tol, eta, max_iters, literal);
+    CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+    CB_HIP(hipStreamSynchronize(s));
+    if (hs->stop) {
+        if (hs->nb == 0.0) launch_fill(x, 0.0, n, s);
+    } else {
+        int cycles = 0;
+        bool capped = false;
+        for (;;) {
+            // restart: explicit residual into w, beta, stop test
+            launch_spmv(A, x, b, w, part, 1, nullptr, s);
+            launch_reduce(part, Gs, 1, &st->r2, 0, nullptr, s);
+            k_cycle_begin<<<1, 64, 0, s>>>(st, flag, g, m);
+            CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+            if (cycles > 0) CB_HIP(hipMemcpyAsync(hh, hist, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+            CB_HIP(hipStreamSynchronize(s));
+            if (history_host && cycles > 0) {
+                for (int k = 0; k < hs->prev_steps && recorded < history_cap; ++k)
+                    history_host[recorded++] = hh[k] / hs->nb;
+            }
+            if (hs->stop) break;
+            // v_1 = r / beta, V_1 = Q(v_1)
+            launch_store(fmt, V, 0, w, &st->beta, v, flag, active, s);
+            for (int j = 0; j < m; ++j) {
+                launch_spmv(A, v, nullptr, w, part, 0, active, s);
+                launch_reduce(part, Gs, 1, &st->om2, 0, active, s);
+                launch_project(fmt, V, j + 1, w, part, active, s);
+                launch_reduce(part, Gb, j + 1, H + (int64_t)j * (m + 1), 0, active, s);
+                launch_subtract(fmt, V, j + 1, nullptr, H + (int64_t)j * (m + 1), w, part, active, -1, s);
+                launch_reduce(part, Gb, 1, &st->hn2, 0, active, s);
+                k_step_check<<<1, 64, 0, s>>>(st, H, cs, sn, g, hist, j, m, cbytes);
+                launch_project(fmt, V, j + 1, w, part, reorth, s);
+                launch_reduce(part, Gb, j + 1, u, 0, reorth, s);
+                launch_subtract(fmt, V, j + 1, nullptr, u, w, part, reorth, -1, s);
+                launch_reduce(part, Gb, 1, &st->hn2, 0, reorth, s);
+                k_step_finish<<<1, 64, 0, s>>>(st, H, u, cs, sn, g, hist, j, m, cbytes);
+                if (j + 1 < m) launch_store(fmt, V, j + 1, w, &st->hn, v, flag, active, s);
+            }
+            k_backsolve<<<1, 64, 0, s>>>(st, H, g, y, m, cbytes);
+            launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, s);
+            CB_HIP(hipGetLastError());
+            ++cycles;
+            if (max_cycles > 0 && cycles >= max_cycles) {
+                CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+                CB_HIP(hipMemcpyAsync(hh, hist, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+                CB_HIP(hipStreamSynchronize(s));
+                if (history_host) {
+                    for (int k = 0; k < hs->steps && recorded < history_cap; ++k)
+                        history_host[recorded++] = hh[k] / hs->nb;
+                }
+                capped = true;
+                break;
+            }
+        }
+        if (capped && hs->status == CB_OK) {
+            // cycle cap: report without the explicit residual of the new x
+            hs->status = CB_ERR_NOT_CONVERGED;
+            hs->rel = -1.0;
+        }
+    }
+    CB_HIP(hipStreamSynchronize(s));
+    if (res) {
+        res->iterations = hs->iters;
+        res->restarts = hs->cycles;
+        res->reorths = hs->reorths;
+        res->breakdowns = hs->breakdowns;
+        res->converged = hs->converged;
+        res->status = hs->status;
+        res->rel_residual = hs->rel;
+        res->implicit_rel_residual = hs->gabs >= 0 ? hs->gabs / (hs->nb > 0 ? hs->nb : 1.0) : -1.0;
+        res->seconds = now_s() - t0;
+        res->basis_bytes = hs->basis_bytes;
+    }
+    return hs->status;
+}
+
+static int check_solve_args(const cb_csr* A, const double* b, const double* x, int32_t m,
+                            double tol, int format) {
+    if (!A || !b || !x) return fail(CB_ERR_INVALID_ARG, "NULL argument");
+    if (A->n < 1 || A->n > INT32_MAX - 64 || A->nnz < 0 || !A->row_ptr || (A->nnz && (!A->col || !A->val)))
+        return fail(CB_ERR_INVALID_ARG, "bad matrix");
+    if (m < 1 || m > 4096) return fail(CB_ERR_INVALID_ARG, "restart m=%d out of range [1, 4096]", m);
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(CB_ERR_INVALID_ARG, "tol must be positive");
+    if (!valid_format(format)) return fail(CB_ERR_INVALID_ARG, "unknown basis format %d", format);
+    return CB_OK;
+}
+
+}  // namespace cb
+
+using namespace cb;
+
+extern "C" {
+
+int64_t cbgmres_workspace_bytes(int32_t n, int32_t m, int format) {
+    if (n < 1 || m < 1 || !valid_format(format)) return -1;
+    return layout_of(n, m, format).total;
+}
+
+int cbgmres_solve(const cb_csr* A, const double* b, double* x, int32_t m, double tol, int format,
+                  const cb_options* opt, void* workspace, size_t workspace_bytes,
+                  double* history_host, int64_t history_cap, cb_result* result_host, void* stream) {
+    if (int e = check_solve_args(A, b, x, m, tol, format)) return e;
+    hipStream_t s = (hipStream_t)stream;
+    Ws W;
+    W.L = layout_of(A->n, m, format);
+    bool owned = false;
+    if (workspace) {
+        if ((int64_t)workspace_bytes < W.L.total)
+            return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", workspace_bytes,
+                        (long long)W.L.total);
+        W.base = static_cast<unsigned char*>(workspace);
+    } else {
+        void* p = nullptr;
+        CB_HIP(hipMalloc(&p, (size_t)W.L.total));
+        W.base = static_cast<unsigned char*>(p);
+        owned = true;
+    }
+    int st = solve_impl(*A, b, x, m, tol, format, opt, W, history_host, history_cap, result_host, s);
+    if (owned) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(W.base);
+    }
+    return st;
+}
+
+int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, double inner_tol,
+                     double tol, int format, int32_t max_outer, cb_result* result_host,
+                     void* stream) {
+    if (int e = check_solve_args(A, b, x, m, tol, format)) return e;
+    if (!(inner_tol > 0.0)) return fail(CB_ERR_INVALID_ARG, "inner_tol must be positive");
+    if (max_outer < 1) return fail(CB_ERR_INVALID_ARG, "max_outer must be >= 1");
+    const double t0 = now_s();
+    hipStream_t s = (hipStream_t)stream;
+    const int n = A->n;
+    Ws W;
+    W.L = layout_of(n, m, format);
+    const int64_t vec = al(padded_rows(n) * 8);
+    void* p = nullptr;
+    CB_HIP(hipMalloc(&p, (size_t)(W.L.total + 2 * vec + 256)));
+    W.base = static_cast<unsigned char*>(p);
+    double* r = reinterpret_cast<double*>(W.base + W.L.total);
+    double* d = reinterpret_cast<double*>(W.base + W.L.total + vec);
+    double* scal = reinterpret_cast<double*>(W.base + W.L.total + 2 * vec);
+    double* part = W.at<double>(W.L.part);
+    const int Gs = spmv_groups(n, A->nnz);
+    double* hv = static_cast<double*>(g_pinned.get(sizeof(State) + (size_t)m * 8 + 64));
+    int status = CB_ERR_NOT_CONVERGED;
+    cb_result acc;
+    memset(&acc, 0, sizeof acc);
+    acc.rel_residual = -1.0;
+    cb_options io{0.0, 0, 1, 0, 0};
+    double nb = 0.0;
+    if (!hv) { status = fail(CB_ERR_HIP, "hipHostMalloc failed"); goto done; }
+    enqueue_sumsq(b, n, part, scal, s);
+    if (hipMemcpyAsync(hv, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { status = fail(CB_ERR_HIP, "copy failed"); goto done; }
+    nb = std::sqrt(hv[0]);
+    if (nb == 0.0) {
+        launch_fill(x, 0.0, n, s);
+        acc.converged = 1;
+        acc.rel_residual = 0.0;
+        status = CB_OK;
+        goto done;
+    }
+    for (;;) {
+        launch_spmv(*A, x, b, r, part, 1, nullptr, s);
+        launch_reduce(part, Gs, 1, scal, 0, nullptr, s);
+        if (hipMemcpyAsync(hv, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { status = fail(CB_ERR_HIP, "copy failed"); goto done; }
+        const double rn = std::sqrt(hv[0]);
+        acc.rel_residual = rn / nb;
+        if (!std::isfinite(rn)) { status = CB_ERR_NONFINITE; break; }
+        if (rn <= tol * nb) { acc.converged = 1; status = CB_OK; break; }
+        if (acc.restarts >= max_outer) { status = CB_ERR_NOT_CONVERGED; break; }
+        launch_fill(d, 0.0, n, s);
+        cb_result ir;
+        int ist = solve_impl(*A, r, d, m, inner_tol, format, &io, W, nullptr, 0, &ir, s);
+        acc.iterations += ir.iterations;
+        acc.reorths += ir.reorths;
+        acc.breakdowns += ir.breakdowns;
+        acc.basis_bytes += ir.basis_bytes;
+        acc.restarts += 1;
+        acc.implicit_rel_residual = ir.implicit_rel_residual;
+        if (ist == CB_ERR_NONFINITE || ist == CB_ERR_HIP) { status = ist; break; }
+        k_axpy<<<(n + 255) / 256, 256, 0, s>>>(x, d, n);
+    }
+done:
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(W.base);
+    acc.status = status;
+    acc.seconds = now_s() - t0;
+    if (result_host) *result_host = acc;
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// CSR sparse matrix-vector product in FP64 (Fig. 1 steps 1 and 3) with the
+// squared norm of the result fused in (step 4).
+//
+// A group of LPR lanes works on one row: lane i of the group accumulates the
+// row's entries i, i+LPR, ... with FMA in CSR order, then the group sums with a
+// fixed shuffle tree.  LPR is the power of two nearest to half the average row
+// length (4 for the 5- and 7-point stencils), so most lanes own one or two
+// nonzeros and the row's column indices are read as one coalesced run.  The
+// row-to-workgroup map depends on the matrix only, keeping the norm's
+// reduction order fixed.
+#include "cb_internal.hpp"
+#include "reduce.hpp"
+
+namespace cb {
+
+using namespace dev;
+
+template <int LPR>
+__global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
+                                              const int* __restrict__ ci,
+                                              const double* __restrict__ val,
+                                              const double* __restrict__ x,
+                                              const double* __restrict__ b, double* __restrict__ y,
+                                              double* __restrict__ partials, int mode,
+                                              const int* __restrict__ guard) {
+    if (guard && *guard == 0) return;
+    constexpr int RPW = 256 / LPR;
+    const int sub = threadIdx.x / LPR;
+    const int li = threadIdx.x % LPR;
+    const int row = blockIdx.x * RPW + sub;
+    double s = 0.0;
+    if (row < n) {
+        const int k1 = rp[row + 1];
+        for (int k = rp[row] + li; k < k1; k += LPR) s = fma(val[k], x[ci[k]], s);
+    }
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+    double out = 0.0;
+    if (row < n && li == 0) {
+        out = mode ? b[row] - s : s;
+        y[row] = out;
+    }
+    if (partials) {
+        double t = block_sum<256>(out * out);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
+int spmv_lanes_per_row(int32_t n, int32_t nnz) {
+    double avg = n > 0 ? (double)nnz / (double)n : 1.0;
+    int lpr = 1;
+    while (lpr < 64 && 2.0 * lpr <= avg) lpr *= 2;
+    return lpr;
+}
+
+int spmv_groups(int32_t n, int32_t nnz) {
+    const int rpw = 256 / spmv_lanes_per_row(n, nnz);
+    return (int)(((int64_t)n + rpw - 1) / rpw);
+}
+
+void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
+                 int mode, const int* guard, hipStream_t s) {
+    const int lpr = spmv_lanes_per_row(A.n, A.nnz);
+    const int G = spmv_groups(A.n, A.nnz);
+#define CB_SPMV_CASE(L)                                                                         \
+    case L:                                                                                     \
+        k_spmv<L><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard); \
+        break;
+    switch (lpr) {
+        CB_SPMV_CASE(1)
+        CB_SPMV_CASE(2)
+        CB_SPMV_CASE(4)
+        CB_SPMV_CASE(8)
+        CB_SPMV_CASE(16)
+        CB_SPMV_CASE(32)
+        default:
+        CB_SPMV_CASE(64)
+    }
+#undef CB_SPMV_CASE
+}
+
+}  // namespace cb

@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/cbgmres.h; host-only size queries agree with the oracle's storage
+definitions; argument errors are reported before any device work (CPU only)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import paper_2409_15468_amd as cb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cbgmres.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set()
+    for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b([a-z][a-z0-9_]*)\s*\(", text, flags=re.M):
+        line = m.group(0)
+        if line.lstrip().startswith(("typedef", "#")):
+            continue
+        names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 25
+    L = cb.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", cb.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert set(names) <= exported
+    assert set(names) == set(cb.SIGNATURES)
+
+
+def test_size_queries_match_storage_definitions():
+    for n in (1, 31, 32, 33, 1000, 1 << 20, 1000003):
+        assert cb.frsz2_exponent_words(n) == (n + 31) // 32
+        for bits in (16, 21, 32):
+            assert cb.frsz2_value_words(n, bits) == bits * ((n + 31) // 32)
+        for fmt in oracle.FORMATS:
+            assert cb.cb_basis_column_bytes(fmt, n) == oracle.col_bytes(fmt, n)
+            ew = cb.cb_basis_exponent_words(fmt, n)
+            assert ew == ((n + 31) // 32 if fmt.startswith("frsz2") else 0)
+    assert cb.frsz2_value_words(10, 17) == -1
+    assert cb.cb_basis_column_bytes(9, 10) == -1
+    assert cb.cbgmres_workspace_bytes(1000, 10, "frsz2_32") > 11 * cb.cb_basis_column_bytes("frsz2_32", 1000)
+    assert cb.Server.request_bytes(1000, 5000, 10, "float32") > cb.cbgmres_workspace_bytes(1000, 10, "float32")
+
+
+def test_argument_errors_without_device_work():
+    L = cb.lib()
+    assert L.frsz2_compress(None, 10, 17, None, None, None, None) == cb.CB_ERR_UNSUPPORTED_BITS
+    assert L.frsz2_compress(None, 10, 32, None, None, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_decompress(None, None, 0, 16, None, None) == cb.CB_ERR_INVALID_ARG
+    assert b"16, 21 or 32" in L.cb_last_error() or L.cb_last_error()
+    A = cb.cb_csr(10, 0, None, None, None)
+    res = cb.cb_result()
+    st = L.cbgmres_solve(C.byref(A), None, None, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res), None)
+    assert st == cb.CB_ERR_INVALID_ARG
+    V = cb.cb_basis(5, 100, 4, 0, None, None)
+    assert L.cb_basis_load(C.byref(V), 0, None, None) == cb.CB_ERR_INVALID_ARG
+    V = cb.cb_basis(7, 100, 4, 0, 1, 1)
+    assert L.cb_basis_load(C.byref(V), 0, 1, None) == cb.CB_ERR_INVALID_ARG
+    for s in range(10):
+        assert L.cb_status_string(s)
