@@ -99,11 +99,12 @@ int frsz2_decompress(const uint32_t* exps, const uint32_t* words, int64_t n, int
  * Compressed basis V = [v_0 .. v_{ncols-1}] (Fig. 1, the highlighted
  * storage sites) and the fused hot-path primitives.
  *
- * Column c of `values` starts at byte c * cb_basis_column_bytes(format, n);
- * frsz2 columns keep their exponents at exps + c * cb_basis_exponent_words.
- * Rows n .. 32*ceil(n/32)-1 of every column are stored as +0.0.  Float
- * columns are float64/float32/binary16 arrays of 32*ceil(n/32) entries; frsz2
- * columns are the `words` array above.  `exps` is ignored (may be NULL) for
+ * Column c of `values` starts at byte c * cb_basis_column_bytes(format, n)
+ * (the column's data rounded up to a multiple of 256 bytes); frsz2 columns
+ * keep their exponents at exps + c * cb_basis_exponent_words.  Rows
+ * n .. 32*ceil(n/32)-1 of every column are stored as +0.0.  Float columns
+ * begin with float64/float32/binary16 arrays of 32*ceil(n/32) entries; frsz2
+ * columns with the `words` array above.  `exps` is ignored (may be NULL) for
  * float formats.
  * ====================================================================== */
 typedef struct cb_basis {
@@ -115,7 +116,7 @@ typedef struct cb_basis {
     uint32_t* exps;   /* device, frsz2 only */
 } cb_basis;
 
-int64_t cb_basis_column_bytes(int format, int64_t n);
+int64_t cb_basis_column_bytes(int format, int64_t n);   /* column stride */
 int64_t cb_basis_exponent_words(int format, int64_t n); /* 0 for float formats */
 
 /* Normalise and store one basis column (Fig. 1 steps 1, 13-14):
@@ -130,7 +131,9 @@ int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double
 int cb_basis_load(const cb_basis* V, int32_t col, double* x, void* stream);
 
 /* Bytes of reduction workspace needed by the primitives below for n rows and
- * up to ncols columns (per-workgroup partial sums). */
+ * up to ncols columns: a 256-byte header (a completion counter the call
+ * resets itself) followed by per-workgroup partial sums.  Calls that share a
+ * workspace must run in stream order. */
 int64_t cb_reduce_workspace_bytes(int32_t n, int32_t ncols);
 
 /* Classical Gram-Schmidt projection with decompression fused into the read
@@ -165,7 +168,9 @@ typedef struct cb_csr {
 } cb_csr;
 
 /* y = A x (Fig. 1 step 3, M = I) and, if norm2 != NULL, *norm2 = ||y||^2
- * (step 4).  Asynchronous. */
+ * (step 4); the norm needs work_bytes >= 256 + 8 * (number of row groups),
+ * 256 + 8 * (n + 1) always suffices.  Column indices must lie in [0, n).
+ * Asynchronous. */
 int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
             size_t work_bytes, void* stream);
 
@@ -206,7 +211,7 @@ typedef struct cb_result {
 int64_t cbgmres_workspace_bytes(int32_t n, int32_t m, int format);
 
 /* Solve A x = b.  x holds x0 on entry and the iterate on return (device,
- * float64[n]).  m >= 1 is the restart length, tol > 0 the relative residual
+ * float64[n]).  1 <= m <= 512 is the restart length, tol > 0 the relative residual
  * ||b - A x|| <= tol ||b|| that ends the solve (checked on the explicit
  * residual at a restart, Eq. 4; the implicit residual only ends a cycle
  * early).  workspace may be NULL (the library allocates and frees it) or a

@@ -214,9 +214,15 @@ class Basis:
     def column_bytes(self) -> int:
         return cb_basis_column_bytes(self.fmt, self.n)
 
+    def column_data_bytes(self) -> int:
+        nb = (self.n + 31) // 32
+        bits = {3: 16, 4: 21, 5: 32}.get(self.fmt)
+        return nb * bits * 4 if bits else nb * 32 * (8, 4, 2)[self.fmt]
+
     def column(self, c: int):
+        """The stored bytes of column c (without the stride padding)."""
         cb = self.column_bytes()
-        return self.values[c * cb:(c + 1) * cb]
+        return self.values[c * cb:c * cb + self.column_data_bytes()]
 
     def column_exps(self, c: int):
         ew = cb_basis_exponent_words(self.fmt, self.n)
@@ -325,8 +331,8 @@ class DeviceCSR:
 
 def _spmv_work(A: DeviceCSR, device):
     import torch
-    nbytes = 8 * (A.n + 1)
-    return torch.empty(A.n + 1, dtype=torch.float64, device=device), nbytes
+    nbytes = 256 + 8 * (A.n + 1)
+    return torch.empty(nbytes // 8, dtype=torch.float64, device=device), nbytes
 
 
 def cb_spmv(A: DeviceCSR, x, y=None, norm2=None, stream=None):

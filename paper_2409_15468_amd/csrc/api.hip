@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "cb_internal.hpp"
+#include "epilogue.hpp"
 
 namespace cb {
 
@@ -24,7 +25,7 @@ int fail(int status, const char* fmt, ...) {
     return status;
 }
 
-int64_t column_bytes(int f, int64_t n) {
+int64_t column_data_bytes(int f, int64_t n) {
     const int64_t nb = nblocks(n);
     switch (f) {
     case CB_F64: return nb * 32 * 8;
@@ -37,12 +38,32 @@ int64_t column_bytes(int f, int64_t n) {
     }
 }
 
+// Column stride: the data rounded up to 256 bytes, so every column starts
+// aligned for 16-byte loads (frsz2_21 tiles are 1344-byte runs).
+int64_t column_bytes(int f, int64_t n) {
+    const int64_t d = column_data_bytes(f, n);
+    return d < 0 ? d : (d + 255) / 256 * 256;
+}
+
 int64_t exponent_words(int f, int64_t n) { return frsz2_bits_of(f) ? nblocks(n) : 0; }
 
+// Workspace of the primitives: a 256-byte header holding the completion
+// counter of the last-workgroup reduction, then the partial sums.
 int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz) {
     int64_t a = (int64_t)row_groups(n) * (ncols > 0 ? ncols : 1);
     int64_t b = nnz > 0 ? spmv_groups(n, nnz) : 0;
-    return 8 * (a > b ? a : b);
+    return 256 + 8 * (a > b ? a : b);
+}
+
+static Epi store_epi(double* out, void* work) {
+    Epi e{};
+    e.mode = EPI_STORE;
+    e.out = out;
+    e.counter = static_cast<unsigned*>(work);
+    return e;
+}
+static double* partials_of(void* work) {
+    return reinterpret_cast<double*>(static_cast<unsigned char*>(work) + 256);
 }
 
 static bool bad_n(int64_t n) { return n < 1 || n > (int64_t)INT32_MAX - 64; }
@@ -157,9 +178,8 @@ int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, voi
         return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", work_bytes,
                     (long long)reduce_workspace_bytes(V->n, j, 0));
     hipStream_t s = (hipStream_t)stream;
-    double* part = static_cast<double*>(work);
-    launch_project(V->format, *V, j, w, part, nullptr, s);
-    launch_reduce(part, row_groups(V->n), j, h, 0, nullptr, s);
+    launch_zero_counter(static_cast<unsigned*>(work), s);
+    launch_project(V->format, *V, j, w, partials_of(work), nullptr, store_epi(h, work), s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }
@@ -172,9 +192,9 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
         return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes",
                     (long long)reduce_workspace_bytes(V->n, 1, 0));
     hipStream_t s = (hipStream_t)stream;
-    double* part = norm2 ? static_cast<double*>(work) : nullptr;
-    launch_subtract(V->format, *V, j, nullptr, h, w, part, nullptr, -1, s);
-    if (norm2) launch_reduce(part, row_groups(V->n), 1, norm2, 0, nullptr, s);
+    if (norm2) launch_zero_counter(static_cast<unsigned*>(work), s);
+    launch_subtract(V->format, *V, j, nullptr, h, w, norm2 ? partials_of(work) : nullptr, nullptr, -1,
+                    store_epi(norm2, work), s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }
@@ -182,7 +202,7 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
 int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !y || !x) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
-    launch_subtract(V->format, *V, j, nullptr, y, x, nullptr, nullptr, +1, (hipStream_t)stream);
+    launch_subtract(V->format, *V, j, nullptr, y, x, nullptr, nullptr, +1, Epi{}, (hipStream_t)stream);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }
@@ -199,13 +219,12 @@ int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* wo
             size_t work_bytes, void* stream) {
     if (int st = check_csr(A)) return st;
     if (!x || !y) return fail(CB_ERR_INVALID_ARG, "NULL vector");
-    const int G = spmv_groups(A->n, A->nnz);
-    if (norm2 && (!work || work_bytes < (size_t)G * 8))
-        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)G * 8);
+    const int64_t need = 256 + 8 * (int64_t)spmv_groups(A->n, A->nnz);
+    if (norm2 && (!work || (int64_t)work_bytes < need))
+        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
     hipStream_t s = (hipStream_t)stream;
-    double* part = norm2 ? static_cast<double*>(work) : nullptr;
-    launch_spmv(*A, x, nullptr, y, part, 0, nullptr, s);
-    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
+    if (norm2) launch_zero_counter(static_cast<unsigned*>(work), s);
+    launch_spmv(*A, x, nullptr, y, norm2 ? partials_of(work) : nullptr, 0, nullptr, store_epi(norm2, work), s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }
@@ -214,13 +233,12 @@ int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, do
                 void* work, size_t work_bytes, void* stream) {
     if (int st = check_csr(A)) return st;
     if (!x || !r || !b) return fail(CB_ERR_INVALID_ARG, "NULL vector");
-    const int G = spmv_groups(A->n, A->nnz);
-    if (norm2 && (!work || work_bytes < (size_t)G * 8))
-        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)G * 8);
+    const int64_t need = 256 + 8 * (int64_t)spmv_groups(A->n, A->nnz);
+    if (norm2 && (!work || (int64_t)work_bytes < need))
+        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
     hipStream_t s = (hipStream_t)stream;
-    double* part = norm2 ? static_cast<double*>(work) : nullptr;
-    launch_spmv(*A, x, b, r, part, 1, nullptr, s);
-    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
+    if (norm2) launch_zero_counter(static_cast<unsigned*>(work), s);
+    launch_spmv(*A, x, b, r, norm2 ? partials_of(work) : nullptr, 1, nullptr, store_epi(norm2, work), s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }

@@ -9,6 +9,7 @@
 // then the workgroups in order) is the same on every run and for every caller.
 #include "cb_internal.hpp"
 #include "codec.hpp"
+#include "epilogue.hpp"
 #include "reduce.hpp"
 
 namespace cb {
@@ -16,6 +17,7 @@ namespace cb {
 using namespace dev;
 
 // ----------------------------------------------------------------- store (encode)
+// Workgroup g, wave w encodes the 512-row tile starting at 2048 g + 512 w.
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ values,
                                                     uint32_t* __restrict__ exps, int n, int np,
@@ -23,129 +25,201 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
                                                     double* v_out, int32_t* __restrict__ flag,
                                                     const int* __restrict__ guard) {
     if (guard && *guard == 0) return;
-    const int row = blockIdx.x * kThreads + threadIdx.x;
-    if (row >= np) return;  // whole 32-lane groups leave together (np % 32 == 0)
-    double v = 0.0;
-    if (row < n) {
-        v = w[row];
-        if (divisor) v = v / *divisor;  // IEEE division per entry
-        if (v_out) v_out[row] = v;
+    using M = Map<FMT>;
+    const int lane = threadIdx.x & 63;
+    const int tile0 = blockIdx.x * kRowsPerWG + (threadIdx.x >> 6) * kTile;
+    double v[8];
+    load_rows<FMT>(w, tile0, lane, n, v);
+    if (divisor) {
+        const double d = *divisor;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = v[q] / d;  // IEEE division per entry
     }
-    if constexpr (FMT == CB_F64) {
-        reinterpret_cast<double*>(values)[row] = v;
-        if (flag && !isfinite(v)) atomicOr(flag, 1);
-    } else if constexpr (FMT == CB_F32) {
-        float f = (float)v;
-        reinterpret_cast<float*>(values)[row] = f;
-        if (flag && !isfinite(f)) atomicOr(flag, 1);
-    } else if constexpr (FMT == CB_F16) {
-        uint32_t h = double_to_half_rne(v);
-        reinterpret_cast<uint16_t*>(values)[row] = (uint16_t)h;
-        if (flag && (h & 0x7C00u) == 0x7C00u) atomicOr(flag, 1);
+    if (v_out) store_rows<FMT>(v_out, tile0, lane, n, v);
+    bool bad = false;
+    if constexpr (FMT == CB_F64 || FMT == CB_F32 || FMT == CB_F16) {
+#pragma unroll
+        for (int k = 0; k < M::NG; ++k) {
+            const int r = tile0 + M::group_row(lane, k);
+            uint4 o;
+            if constexpr (FMT == CB_F64) {
+                const double a = v[2 * k], b = v[2 * k + 1];
+                o = make_uint4(lo32(a), hi32(a), lo32(b), hi32(b));
+                bad |= !isfinite(a) || !isfinite(b);
+            } else if constexpr (FMT == CB_F32) {
+                float f[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    f[i] = (float)v[4 * k + i];
+                    bad |= !isfinite(f[i]);
+                }
+                o = make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
+                               __float_as_uint(f[3]));
+            } else {
+                uint32_t h[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    h[i] = double_to_half_rne(v[i]);
+                    bad |= (h[i] & 0x7C00u) == 0x7C00u;
+                }
+                o = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
+            }
+            constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
+            if (r < np) *reinterpret_cast<uint4*>(values + (int64_t)r * esz) = o;
+        }
+    } else if constexpr (FMT == CB_FRSZ2_32) {
+        // groups of 4 values; the 8 lanes 8u..8u+7 hold one block
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = tile0 + M::group_row(lane, k);
+            uint32_t E = max(max(exp_field(v[4 * k]), exp_field(v[4 * k + 1])),
+                             max(exp_field(v[4 * k + 2]), exp_field(v[4 * k + 3])));
+            E = group_max<3>(E);  // step 1: block maximum
+            uint4 o = make_uint4(frsz2_code<32>(v[4 * k], E), frsz2_code<32>(v[4 * k + 1], E),
+                                 frsz2_code<32>(v[4 * k + 2], E), frsz2_code<32>(v[4 * k + 3], E));
+            if (r < np) {
+                *reinterpret_cast<uint4*>(values + (int64_t)r * 4) = o;
+                if ((lane & 7) == 0) exps[r >> 5] = E;
+            }
+            bad |= E == 0x7FFu;
+        }
     } else {
-        constexpr int L = FMT == CB_FRSZ2_16 ? 16 : FMT == CB_FRSZ2_21 ? 21 : 32;
-        const int lane = threadIdx.x & 31;
-        const int blk = row >> 5;
-        uint32_t E;
-        const uint32_t c = frsz2_encode_lane<L>(v, &E);
-        if (lane == 0) {
-            exps[blk] = E;
-            if (flag && E == 0x7FFu) atomicOr(flag, 1);
-        }
-        if constexpr (L == 32) {
-            reinterpret_cast<uint32_t*>(values)[row] = c;
-        } else if constexpr (L == 16) {
-            reinterpret_cast<uint16_t*>(values)[row] = (uint16_t)c;
+        // 8 values per lane; the 4 lanes 4u..4u+3 hold one block
+        const int r = tile0 + 8 * lane;
+        uint32_t E = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) E = max(E, exp_field(v[q]));
+        E = group_max<2>(E);
+        bad = E == 0x7FFu;
+        if constexpr (FMT == CB_FRSZ2_16) {
+            uint32_t c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = frsz2_code<16>(v[q], E);
+            if (r < np) {
+                *reinterpret_cast<uint4*>(values + (int64_t)r * 2) =
+                    make_uint4(c[0] | c[1] << 16, c[2] | c[3] << 16, c[4] | c[5] << 16, c[6] | c[7] << 16);
+                if ((lane & 3) == 0) exps[r >> 5] = E;
+            }
         } else {
-            // word k of the block holds stream bits [32k, 32k+32): pieces of the
-            // codes q0 = floor(32k/21), q0+1 and q0+2
-            const int q0 = (32 * lane) / 21;
-            const uint32_t c0 = (uint32_t)__shfl((int)c, q0, 32);
-            const uint32_t c1 = (uint32_t)__shfl((int)c, min(q0 + 1, 31), 32);
-            const uint32_t c2 = (uint32_t)__shfl((int)c, min(q0 + 2, 31), 32);
-            const uint64_t stream = (uint64_t)c0 | ((uint64_t)(q0 + 1 < 32 ? c1 : 0u) << 21) |
-                                    ((uint64_t)(q0 + 2 < 32 ? c2 : 0u) << 42);
-            if (lane < 21)
-                reinterpret_cast<uint32_t*>(values)[blk * 21 + lane] =
-                    (uint32_t)(stream >> (32 * lane - 21 * q0));
+            uint32_t c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = frsz2_code<21>(v[q], E);
+            // the 8 codes as a 168-bit stream, code q at bit 21 q
+            uint32_t S[6];
+            S[0] = c[0] | c[1] << 21;
+            S[1] = c[1] >> 11 | c[2] << 10 | c[3] << 31;
+            S[2] = c[3] >> 1 | c[4] << 20;
+            S[3] = c[4] >> 12 | c[5] << 9 | c[6] << 30;
+            S[4] = c[6] >> 2 | c[7] << 19;
+            S[5] = c[7] >> 13;
+            // placed at bit 8 s of block word 5 s (s = lane % 4): W[k] is word 5 s + k
+            const uint32_t sh = 8u * (lane & 3);
+            uint32_t W[6];
+            W[0] = S[0] << sh;
+#pragma unroll
+            for (int k = 1; k < 6; ++k) W[k] = sh ? ((S[k] << sh) | (S[k - 1] >> (32u - sh))) : S[k];
+            // word 5 s + 5 is shared with the next lane of the block
+            const uint32_t next0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)W[0], 0xF9, 0xF, 0xF, false);
+            if ((lane & 3) != 3) W[5] |= next0;
+            if (r < np) {
+                uint32_t* blk = reinterpret_cast<uint32_t*>(values) + (int64_t)(r >> 5) * 21 + 5 * (lane & 3);
+                if ((lane & 3) == 0) {
+                    blk[0] = W[0];
+                    exps[r >> 5] = E;
+                }
+#pragma unroll
+                for (int k = 1; k < 6; ++k) blk[k] = W[k];
+            }
         }
     }
+    if (flag && bad) atomicOr(flag, 1);
 }
 
 // ----------------------------------------------------------------- load (decode)
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double* __restrict__ x) {
-    const int row0 = blockIdx.x * kRowsPerWG + threadIdx.x * kSeg;
-    if (row0 >= V.np) return;
-    Seg<FMT> s;
-    seg_load(s, V, col, row0);
-    double out[kSeg];
-    s.decode(out);
-    if (row0 + kSeg <= V.n) {
-        double2* p = reinterpret_cast<double2*>(x + row0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) p[k] = make_double2(out[2 * k], out[2 * k + 1]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < kSeg; ++q)
-            if (row0 + q < V.n) x[row0 + q] = out[q];
-    }
-}
-
-__device__ __forceinline__ void load_w(const double* __restrict__ w, int row0, int n, double* wv) {
-    if (row0 + kSeg <= n) {
-        const double2* p = reinterpret_cast<const double2*>(w + row0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double2 t = p[k];
-            wv[2 * k] = t.x;
-            wv[2 * k + 1] = t.y;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kSeg; ++q) wv[q] = (row0 + q < n) ? w[row0 + q] : 0.0;
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile0 = blockIdx.x * kRowsPerWG + wave * kTile;
+    Tile<FMT> t[1];
+    const int cols[1] = {col};
+    if (tile0 + kTile <= V.np) load_tiles<FMT, 1, true>(t, V, cols, tile0, lane);
+    else load_tiles<FMT, 1, false>(t, V, cols, tile0, lane);
+    double out[8];
+    t[0].decode(out);
+    store_rows<FMT>(x, tile0, lane, V.n, out);
 }
 
 // ----------------------------------------------------------------- CGS projection
-// partials[c * G + g] = sum over the workgroup's rows of D(v_c) * w, c < j.
-template <int FMT, int U>
+// One wave's columns [c0, c1) of its tile, 8 at a time; the wave's sums for
+// column c land in red[c - c0].  The loads of the next 8 columns are issued
+// before the current 8 are reduced across the wave.
+template <int FMT, bool FULL>
+__device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1, int tile0, int lane,
+                                             const double* wv, double* red) {
+    Tile<FMT> t[8];
+    int cols[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cols[u] = min(c0 + u, c1 - 1);
+    load_tiles<FMT, 8, FULL>(t, V, cols, tile0, lane);
+    for (int c = c0; c < c1; c += 8) {
+        double p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = t[u].dot(wv);
+        if (c + 8 < c1) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cols[u] = min(c + 8 + u, c1 - 1);
+            load_tiles<FMT, 8, FULL>(t, V, cols, tile0, lane);
+        }
+        const double sum = wave_sum8(p);  // lane 8u holds column c + u
+        if ((lane & 7) == 0 && c + (lane >> 3) < c1) red[c + (lane >> 3) - c0] = sum;
+    }
+}
+
+// partials[c * G + g] = sum over the workgroup's rows of D(v_c) * w, c < j;
+// the last workgroup then forms the sums over g (see epilogue.hpp).
+template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ partials, int G,
-                                                      const int* __restrict__ guard) {
+                                                      const int* __restrict__ guard, Epi e) {
     if (guard && *guard == 0) return;
     __shared__ double red[kThreads / 64][kColChunk];
+    __shared__ double elds[kEpiLds];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.x;
     const int c0 = blockIdx.y * kColChunk;
     const int c1 = min(j, c0 + kColChunk);
-    int row0 = g * kRowsPerWG + tid * kSeg;
-    const bool live = row0 < V.np;
-    if (!live) row0 = 0;  // keep loads in bounds; the lane contributes 0
-    double wv[kSeg];
-    load_w(w, live ? row0 : V.n, V.n, wv);
-    for (int c = c0; c < c1; c += U) {
-        Seg<FMT> s[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) seg_load(s[u], V, min(c + u, c1 - 1), row0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            double p = (live && c + u < c1) ? s[u].dot(wv) : 0.0;
-            p = wave_sum(p);
-            if (lane == 0 && c + u < c1) red[wave][c + u - c0] = p;
-        }
-    }
+    const int tile0 = g * kRowsPerWG + wave * kTile;
+    double wv[8];
+    load_rows<FMT>(w, tile0, lane, V.n, wv);
+    if (tile0 + kTile <= V.np) project_tile<FMT, true>(V, c0, c1, tile0, lane, wv, red[wave]);
+    else project_tile<FMT, false>(V, c0, c1, tile0, lane, wv, red[wave]);
     __syncthreads();
     for (int i = tid; i < c1 - c0; i += kThreads) {
-        double t = red[0][i];
+        double s = red[0][i];
 #pragma unroll
-        for (int k = 1; k < kThreads / 64; ++k) t += red[k][i];
-        partials[(int64_t)(c0 + i) * G + g] = t;
+        for (int k = 1; k < kThreads / 64; ++k) s += red[k][i];
+        store_partial(partials + (int64_t)(c0 + i) * G + g, s);
     }
+    epilogue(e, partials, elds);
 }
 
 // ----------------------------------------------------------------- CGS update / x update
+template <int FMT, int U, bool FULL>
+__device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const double* __restrict__ h,
+                                              int tile0, int lane, double* acc) {
+    for (int c = 0; c < j; c += U) {
+        Tile<FMT> t[U];
+        int cols[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
+        load_tiles<FMT, U, FULL>(t, V, cols, tile0, lane);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
+    }
+}
+
 // w[k] += sign * sum_{c<j} h[c] * D(v_c)[k]; partials[g] = sum of w[k]^2 over
 // the workgroup's rows after the update (if partials != NULL).
 template <int FMT, int U>
@@ -153,48 +227,30 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
                                                        const double* __restrict__ h,
                                                        double* __restrict__ w,
                                                        double* __restrict__ partials, int sign,
-                                                       const int* __restrict__ guard) {
+                                                       const int* __restrict__ guard, Epi e) {
     if (guard && *guard == 0) return;
     if (jdev) j = *jdev;
-    const int tid = threadIdx.x;
-    int row0 = blockIdx.x * kRowsPerWG + tid * kSeg;
-    const bool live = row0 < V.np;
-    if (!live) row0 = 0;
-    double acc[kSeg];
+    __shared__ double elds[kEpiLds];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile0 = blockIdx.x * kRowsPerWG + wave * kTile;
+    double acc[8];
 #pragma unroll
-    for (int q = 0; q < kSeg; ++q) acc[q] = 0.0;
-    for (int c = 0; c < j; c += U) {
-        Seg<FMT> s[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) seg_load(s[u], V, min(c + u, j - 1), row0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double hc = (c + u < j) ? h[c + u] : 0.0;
-            if (c + u < j) s[u].axpy(hc, acc);
-        }
-    }
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    if (tile0 + kTile <= V.np) subtract_tile<FMT, U, true>(V, j, h, tile0, lane, acc);
+    else subtract_tile<FMT, U, false>(V, j, h, tile0, lane, acc);
+    double wv[8];
+    load_rows<FMT>(w, tile0, lane, V.n, wv);
     double nrm = 0.0;
-    if (live) {
-        double wv[kSeg];
-        load_w(w, row0, V.n, wv);
 #pragma unroll
-        for (int q = 0; q < kSeg; ++q) {
-            wv[q] = sign > 0 ? wv[q] + acc[q] : wv[q] - acc[q];
-            if (row0 + q < V.n) nrm = fma(wv[q], wv[q], nrm);
-        }
-        if (row0 + kSeg <= V.n) {
-            double2* p = reinterpret_cast<double2*>(w + row0);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) p[k] = make_double2(wv[2 * k], wv[2 * k + 1]);
-        } else {
-#pragma unroll
-            for (int q = 0; q < kSeg; ++q)
-                if (row0 + q < V.n) w[row0 + q] = wv[q];
-        }
+    for (int q = 0; q < 8; ++q) {
+        wv[q] = sign > 0 ? wv[q] + acc[q] : wv[q] - acc[q];
+        nrm = fma(wv[q], wv[q], nrm);  // rows >= n hold 0
     }
+    store_rows<FMT>(w, tile0, lane, V.n, wv);
     if (partials) {
-        double t = block_sum<kThreads>(nrm);
-        if (tid == 0) partials[blockIdx.x] = t;
+        const double t = block_sum<kThreads>(nrm);
+        if (tid == 0) store_partial(partials + blockIdx.x, t);
+        epilogue(e, partials, elds);
     }
 }
 
@@ -226,17 +282,16 @@ __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
     default: { constexpr int F = CB_FRSZ2_32; KERNEL_CALL; break; }          \
     }
 
-template <int F>
-constexpr int unroll_of() {
-    return F == CB_F64 ? 4 : 8;
-}
+__global__ void k_zero(unsigned* __restrict__ c) { *c = 0u; }
+
+void launch_zero_counter(unsigned* counter, hipStream_t s) { k_zero<<<1, 1, 0, s>>>(counter); }
 
 void launch_store(int fmt, const cb_basis& V, int col, const double* w, const double* divisor,
                   double* v_out, int32_t* flag, const int* guard, hipStream_t s) {
     BasisView b = view_of(V);
     unsigned char* vals = static_cast<unsigned char*>(V.values) + (int64_t)col * b.col_bytes;
     uint32_t* ex = V.exps ? V.exps + (int64_t)col * b.exp_stride : nullptr;
-    dim3 grid((unsigned)((b.np + kThreads - 1) / kThreads));
+    dim3 grid((unsigned)row_groups(V.n));
     CB_DISPATCH(fmt, (k_store<F><<<grid, kThreads, 0, s>>>(vals, ex, b.n, b.np, w, divisor, v_out,
                                                            flag, guard)));
 }
@@ -248,20 +303,25 @@ void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s) 
 }
 
 void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* partials,
-                    const int* guard, hipStream_t s) {
+                    const int* guard, const Epi& e, hipStream_t s) {
     BasisView b = view_of(V);
     const int G = row_groups(V.n);
     dim3 grid((unsigned)G, (unsigned)((j + kColChunk - 1) / kColChunk));
-    CB_DISPATCH(fmt, (k_project<F, unroll_of<F>()><<<grid, kThreads, 0, s>>>(b, j, w, partials, G,
-                                                                              guard)));
+    Epi ee = e;
+    ee.G = G;
+    ee.ncols = j;
+    CB_DISPATCH(fmt, (k_project<F><<<grid, kThreads, 0, s>>>(b, j, w, partials, G, guard, ee)));
 }
 
 void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const double* h,
-                     double* w, double* partials, const int* guard, int sign, hipStream_t s) {
+                     double* w, double* partials, const int* guard, int sign, const Epi& e,
+                     hipStream_t s) {
     BasisView b = view_of(V);
     dim3 grid((unsigned)row_groups(V.n));
-    CB_DISPATCH(fmt, (k_subtract<F, unroll_of<F>()><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials,
-                                                                               sign, guard)));
+    Epi ee = e;
+    ee.G = row_groups(V.n);
+    ee.ncols = 1;
+    CB_DISPATCH(fmt, (k_subtract<F, 4><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials, sign, guard, ee)));
 }
 
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op, const int* guard,

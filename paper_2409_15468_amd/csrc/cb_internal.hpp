@@ -29,6 +29,7 @@ constexpr int kSeg = 8;           // rows per thread in the row-segment kernels
 constexpr int kThreads = 256;     // threads per workgroup in the row kernels
 constexpr int kRowsPerWG = kThreads * kSeg;  // 2048 rows = 64 FRSZ2 blocks
 constexpr int kColChunk = 64;     // basis columns per workgroup (grid.y tiles more)
+constexpr int kMaxRestart = 512;  // largest restart length m
 
 inline int64_t nblocks(int64_t n) { return (n + kBS - 1) / kBS; }
 inline int64_t padded_rows(int64_t n) { return nblocks(n) * kBS; }
@@ -38,7 +39,8 @@ inline bool valid_format(int f) { return f >= CB_F64 && f <= CB_FRSZ2_32; }
 inline int frsz2_bits_of(int f) {
     return f == CB_FRSZ2_16 ? 16 : f == CB_FRSZ2_21 ? 21 : f == CB_FRSZ2_32 ? 32 : 0;
 }
-int64_t column_bytes(int f, int64_t n);
+int64_t column_bytes(int f, int64_t n);       // column stride (256-byte multiple)
+int64_t column_data_bytes(int f, int64_t n);  // bytes of one column's values
 int64_t exponent_words(int f, int64_t n);
 
 // Device view of a basis (column-major, see cbgmres.h).
@@ -66,25 +68,31 @@ int spmv_lanes_per_row(int32_t n, int32_t nnz);
 int spmv_groups(int32_t n, int32_t nnz);
 int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz);
 
+struct Epi;  // last-workgroup reduction / solver step logic (epilogue.hpp)
+
 // ---------------------------------------------------------------- launchers (no validation)
 // `guard` (nullable device int): a kernel whose guard reads 0 does nothing.
 // `jdev` (nullable device int): column count read on the device (overrides j).
 void launch_store(int fmt, const cb_basis& V, int col, const double* w, const double* divisor,
                   double* v_out, int32_t* flag, const int* guard, hipStream_t s);
 void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s);
-// Stage 1 of h = V^T w: partials[c * G + g] for c < j.
+// h = V^T w: partials[c * G + g] for c < j, then the epilogue e (its counter
+// must read 0) forms and uses the sums.
 void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* partials,
-                    const int* guard, hipStream_t s);
-// w -= V h (h device), norm partials[g] (nullable).
+                    const int* guard, const Epi& e, hipStream_t s);
+// w += sign * V h (h device); with partials != NULL also ||w||^2 per
+// workgroup and the epilogue e on it.
 void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const double* h,
                      double* w, double* partials, const int* guard, int accumulate_sign,
-                     hipStream_t s);
+                     const Epi& e, hipStream_t s);
+void launch_zero_counter(unsigned* counter, hipStream_t s);
 // Stage 2: out[c] (op 0: =, op 1: +=) = sum_g partials[c * G + g], c < ncols.
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op,
                    const int* guard, hipStream_t s);
-// y = A x (mode 0) or y = b - A x (mode 1); norm partials (nullable).
+// y = A x (mode 0) or y = b - A x (mode 1); with partials != NULL also
+// ||y||^2 per workgroup and the epilogue e on it.
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
-                 int mode, const int* guard, hipStream_t s);
+                 int mode, const int* guard, const Epi& e, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 
 }  // namespace cb

@@ -1,19 +1,21 @@
-// Device-side storage codecs for one basis column: FRSZ2 (l = 16, 21, 32) and
-// the float64/float32/float16 baselines.
+// Device-side storage codecs for basis columns: FRSZ2 (l = 16, 21, 32) and the
+// float64 / float32 / float16 baselines.
 //
-// Reading side: a thread owns a segment of 8 consecutive rows (row0 % 8 == 0),
-// issues the loads for a column in `load`, and consumes them in `dot` (sum of
-// decoded value times w), `axpy` (acc += h * decoded value) or `decode`.
-// FRSZ2 values are never materialised with their scale: each code becomes the
-// exact signed integer +-M (a 32-bit convert plus a sign-bit insert), the
-// segment's products are accumulated, and the block scale 2^(E_eff-1023-(l-2))
-// is applied once per segment with ldexp.  Scaling by a power of two is exact,
-// so this equals decoding first (Eq. 2) up to the order of the sums.
+// Access pattern.  A wavefront works on a tile of 512 consecutive rows of a
+// column; lane t owns 8 of them.  The lane-to-row map is chosen per format so
+// that every 16-byte load instruction of the wave reads one contiguous 1 KB
+// run of the column (lane t at byte 16 t of the run): float64 lanes own rows
+// {128k + 2t, +1}, k < 4; float32 and frsz2_32 lanes own {256k + 4t .. +3},
+// k < 2; float16, frsz2_16 and frsz2_21 lanes own 8t .. 8t+7.  Each such group
+// of rows lies inside one 32-value FRSZ2 block.  frsz2_21 codes straddle words:
+// a lane loads the 6 words that hold its 8 codes.  Basis loads are
+// non-temporal: each pass streams the basis once.
 //
-// Writing side: a 32-lane group holds one FRSZ2 block (Section III-A): the
-// block's largest exponent is found with lane shuffles across the group, then
-// each lane aligns its significand to it, truncates to l-1 bits, prepends the
-// sign and the group packs the codes LSB-first into l words.
+// FRSZ2 values are never materialised with their scale: a code becomes the
+// exact signed integer +-M (a 32-bit convert and a sign-bit insert), products
+// are accumulated, and the block scale 2^(max(E,1)-1023-(l-2)) of Eq. 2 is
+// applied once per block piece with ldexp.  Scaling by a power of two is
+// exact, so this equals decoding first up to the order of the sums.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,18 +27,27 @@
 namespace cb {
 namespace dev {
 
+constexpr int kTile = 512;  // rows of a column per wavefront
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 ld_stream(const void* p) {
+    u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t word_of(const uint4& a, int i) {
+    return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? a.z : a.w;
+}
 __device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__double2loint(x); }
 __device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)__double2hiint(x); }
 __device__ __forceinline__ double make_double(uint32_t hi, uint32_t lo) {
     return __hiloint2double((int)hi, (int)lo);
 }
-
 // (-1)^s * M as a double, exact for M < 2^32; the sign is bit 31 of `sbits`.
 __device__ __forceinline__ double signed_mag(uint32_t M, uint32_t sbits) {
     double d = (double)M;
     return make_double(hi32(d) | (sbits & 0x80000000u), lo32(d));
 }
-
 __device__ __forceinline__ double half_to_double(uint32_t h16) {
     _Float16 hv = __builtin_bit_cast(_Float16, (unsigned short)h16);
     return (double)(float)hv;
@@ -71,47 +82,94 @@ __device__ __forceinline__ uint32_t double_to_half_rne(double x) {
     return sign | q;
 }
 
-// ----------------------------------------------------------------- reading segments
+// ----------------------------------------------------------------- lane-to-row maps
 template <int FMT>
-struct Seg;
-
-template <>
-struct Seg<CB_F64> {
-    double2 x[4];
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
-        const double2* p = reinterpret_cast<const double2*>(V.values + (int64_t)col * V.col_bytes) + (row0 >> 1);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = p[k];
-    }
-    __device__ __forceinline__ double v(int q) const { return (q & 1) ? x[q >> 1].y : x[q >> 1].x; }
-    __device__ __forceinline__ double dot(const double* w) const {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s = fma(v(q), w[q], s);
-        return s;
-    }
-    __device__ __forceinline__ void axpy(double h, double* acc) const {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = fma(h, v(q), acc[q]);
-    }
-    __device__ __forceinline__ void decode(double* out) const {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) out[q] = v(q);
-    }
+struct Map {
+    // rows of lane t: 8 values in NG groups of GS consecutive rows, group k
+    // starting at k * GSTRIDE + GS * t (relative to the tile)
+    static constexpr int GS = FMT == CB_F64 ? 2 : (FMT == CB_F32 || FMT == CB_FRSZ2_32) ? 4 : 8;
+    static constexpr int NG = 8 / GS;
+    static constexpr int GSTRIDE = 64 * GS;
+    __device__ static int row(int t, int q) { return (q / GS) * GSTRIDE + GS * t + (q % GS); }
+    __device__ static int group_row(int t, int k) { return k * GSTRIDE + GS * t; }
 };
 
-template <>
-struct Seg<CB_F32> {
-    float4 x[2];
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
-        const float4* p = reinterpret_cast<const float4*>(V.values + (int64_t)col * V.col_bytes) + (row0 >> 2);
-        x[0] = p[0];
-        x[1] = p[1];
+// w (float64) at the lane's 8 rows; rows >= n read as 0.
+template <int FMT>
+__device__ __forceinline__ void load_rows(const double* __restrict__ w, int tile0, int lane, int n,
+                                          double* wv) {
+    using M = Map<FMT>;
+#pragma unroll
+    for (int k = 0; k < M::NG; ++k) {
+        const int r = tile0 + M::group_row(lane, k);
+        if (r + M::GS <= n) {
+#pragma unroll
+            for (int p = 0; p < M::GS; p += 2) {
+                double2 t = *reinterpret_cast<const double2*>(w + r + p);
+                wv[k * M::GS + p] = t.x;
+                wv[k * M::GS + p + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < M::GS; ++p) wv[k * M::GS + p] = (r + p < n) ? w[r + p] : 0.0;
+        }
+    }
+}
+
+template <int FMT>
+__device__ __forceinline__ void store_rows(double* __restrict__ w, int tile0, int lane, int n,
+                                           const double* wv) {
+    using M = Map<FMT>;
+#pragma unroll
+    for (int k = 0; k < M::NG; ++k) {
+        const int r = tile0 + M::group_row(lane, k);
+        if (r + M::GS <= n) {
+#pragma unroll
+            for (int p = 0; p < M::GS; p += 2)
+                *reinterpret_cast<double2*>(w + r + p) = make_double2(wv[k * M::GS + p], wv[k * M::GS + p + 1]);
+        } else {
+#pragma unroll
+            for (int p = 0; p < M::GS; ++p)
+                if (r + p < n) w[r + p] = wv[k * M::GS + p];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- reading tiles
+// Tile<FMT>: one column's data for the lane's 8 rows.
+//   load(V, col, tile0, lane, lds)  issue the loads (lds: per-wave scratch, frsz2_21)
+//   dot(w)                          sum_q D(v)[q] * w[q]
+//   axpy(h, acc)                    acc[q] += h * D(v)[q]
+//   decode(out)                     out[q] = D(v)[q]
+// Groups of rows past the padded length np are not loaded and read as 0.
+template <int FMT>
+struct Tile;
+
+template <int FMT>
+struct FloatTile {
+    using M = Map<FMT>;
+    uint4 x[M::NG];
+    template <bool FULL>
+    __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
+        const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
+        constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
+#pragma unroll
+        for (int k = 0; k < M::NG; ++k) {
+            const int r = tile0 + M::group_row(lane, k);
+            x[k] = (FULL || r < V.np) ? ld_stream(base + (int64_t)r * esz) : make_uint4(0, 0, 0, 0);
+        }
     }
     __device__ __forceinline__ double v(int q) const {
-        const float4& a = x[q >> 2];
-        float f = (q & 3) == 0 ? a.x : (q & 3) == 1 ? a.y : (q & 3) == 2 ? a.z : a.w;
-        return (double)f;
+        const uint4& a = x[q / M::GS];
+        const int i = q % M::GS;
+        if constexpr (FMT == CB_F64) {
+            return i == 0 ? make_double(a.y, a.x) : make_double(a.w, a.z);
+        } else if constexpr (FMT == CB_F32) {
+            return (double)__uint_as_float(word_of(a, i));
+        } else {
+            uint32_t wd = word_of(a, i >> 1);
+            return half_to_double((i & 1) ? (wd >> 16) : (wd & 0xFFFFu));
+        }
     }
     __device__ __forceinline__ double dot(const double* w) const {
         double s = 0.0;
@@ -128,88 +186,73 @@ struct Seg<CB_F32> {
         for (int q = 0; q < 8; ++q) out[q] = v(q);
     }
 };
+template <> struct Tile<CB_F64> : FloatTile<CB_F64> {};
+template <> struct Tile<CB_F32> : FloatTile<CB_F32> {};
+template <> struct Tile<CB_F16> : FloatTile<CB_F16> {};
+
+__device__ __forceinline__ int scale_exp(uint32_t E, int L) { return (E ? (int)E : 1) - 1023 - (L - 2); }
 
 template <>
-struct Seg<CB_F16> {
-    uint4 x;
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
-        x = *(reinterpret_cast<const uint4*>(V.values + (int64_t)col * V.col_bytes) + (row0 >> 3));
-    }
-    __device__ __forceinline__ double v(int q) const {
-        uint32_t wd = (q >> 1) == 0 ? x.x : (q >> 1) == 1 ? x.y : (q >> 1) == 2 ? x.z : x.w;
-        return half_to_double((q & 1) ? (wd >> 16) : (wd & 0xFFFFu));
-    }
-    __device__ __forceinline__ double dot(const double* w) const {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s = fma(v(q), w[q], s);
-        return s;
-    }
-    __device__ __forceinline__ void axpy(double h, double* acc) const {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = fma(h, v(q), acc[q]);
-    }
-    __device__ __forceinline__ void decode(double* out) const {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) out[q] = v(q);
-    }
-};
-
-// Common part of the FRSZ2 segments: block exponent and the code magnitudes
-// as exact signed doubles.
-template <int L>
-struct FrszBase {
-    uint32_t e;  // stored block exponent field E
-    __device__ __forceinline__ int scale_exp() const {
-        int Eeff = e ? (int)e : 1;
-        return Eeff - 1023 - (L - 2);
-    }
-};
-
-template <>
-struct Seg<CB_FRSZ2_32> : FrszBase<32> {
+struct Tile<CB_FRSZ2_32> {
+    using M = Map<CB_FRSZ2_32>;
     uint4 x[2];
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
-        const uint4* p = reinterpret_cast<const uint4*>(V.values + (int64_t)col * V.col_bytes) + (row0 >> 2);
-        x[0] = p[0];
-        x[1] = p[1];
-        e = V.exps[(int64_t)col * V.exp_stride + (row0 >> 5)];
-    }
-    __device__ __forceinline__ uint32_t code(int q) const {
-        const uint4& a = x[q >> 2];
-        return (q & 3) == 0 ? a.x : (q & 3) == 1 ? a.y : (q & 3) == 2 ? a.z : a.w;
+    uint32_t e[2];
+    template <bool FULL>
+    __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
+        const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
+        const uint32_t* ex = V.exps + (int64_t)col * V.exp_stride;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = tile0 + M::group_row(lane, k);
+            const bool live = FULL || r < V.np;
+            x[k] = live ? ld_stream(base + (int64_t)r * 4) : make_uint4(0, 0, 0, 0);
+            e[k] = live ? ex[r >> 5] : 0u;
+        }
     }
     __device__ __forceinline__ double m(int q) const {
-        uint32_t c = code(q);
+        uint32_t c = word_of(x[q >> 2], q & 3);
         return signed_mag(c & 0x7FFFFFFFu, c);
     }
     __device__ __forceinline__ double dot(const double* w) const {
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s = fma(m(q), w[q], s);
-        return ldexp(s, scale_exp());
+        for (int k = 0; k < 2; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) t = fma(m(4 * k + i), w[4 * k + i], t);
+            s += ldexp(t, scale_exp(e[k], 32));
+        }
+        return s;
     }
     __device__ __forceinline__ void axpy(double h, double* acc) const {
-        double hs = ldexp(h, scale_exp());
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = fma(hs, m(q), acc[q]);
+        for (int k = 0; k < 2; ++k) {
+            const double hs = ldexp(h, scale_exp(e[k], 32));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[4 * k + i] = fma(hs, m(4 * k + i), acc[4 * k + i]);
+        }
     }
     __device__ __forceinline__ void decode(double* out) const {
-        int se = scale_exp();
 #pragma unroll
-        for (int q = 0; q < 8; ++q) out[q] = ldexp(m(q), se);
+        for (int q = 0; q < 8; ++q) out[q] = ldexp(m(q), scale_exp(e[q >> 2], 32));
     }
 };
 
 template <>
-struct Seg<CB_FRSZ2_16> : FrszBase<16> {
+struct Tile<CB_FRSZ2_16> {
+    using M = Map<CB_FRSZ2_16>;
     uint4 x;
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
-        x = *(reinterpret_cast<const uint4*>(V.values + (int64_t)col * V.col_bytes) + (row0 >> 3));
-        e = V.exps[(int64_t)col * V.exp_stride + (row0 >> 5)];
+    uint32_t e;
+    template <bool FULL>
+    __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
+        const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
+        const int r = tile0 + M::group_row(lane, 0);
+        const bool live = FULL || r < V.np;
+        x = live ? ld_stream(base + (int64_t)r * 2) : make_uint4(0, 0, 0, 0);
+        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
     }
     __device__ __forceinline__ double m(int q) const {
-        uint32_t wd = (q >> 1) == 0 ? x.x : (q >> 1) == 1 ? x.y : (q >> 1) == 2 ? x.z : x.w;
+        uint32_t wd = word_of(x, q >> 1);
         if (q & 1) return signed_mag((wd >> 16) & 0x7FFFu, wd);
         return signed_mag(wd & 0x7FFFu, wd << 16);
     }
@@ -217,37 +260,42 @@ struct Seg<CB_FRSZ2_16> : FrszBase<16> {
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) s = fma(m(q), w[q], s);
-        return ldexp(s, scale_exp());
+        return ldexp(s, scale_exp(e, 16));
     }
     __device__ __forceinline__ void axpy(double h, double* acc) const {
-        double hs = ldexp(h, scale_exp());
+        const double hs = ldexp(h, scale_exp(e, 16));
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = fma(hs, m(q), acc[q]);
     }
     __device__ __forceinline__ void decode(double* out) const {
-        int se = scale_exp();
+        const int se = scale_exp(e, 16);
 #pragma unroll
         for (int q = 0; q < 8; ++q) out[q] = ldexp(m(q), se);
     }
 };
 
-// l = 21: a block's 32 codes span 21 words.  The segment of 8 values that
-// starts at value 8t (t = 0..3) begins at bit 168t = 32*(5t) + 8t, so the thread
-// loads the 6 words from 5t and funnel-shifts the window right by 8t bits; the
-// codes then sit at the fixed bit offsets 21q of the shifted 168-bit window.
+// frsz2_21.  The lane's 8 values 8t .. 8t+7 are codes 8s .. 8s+7 (s = t % 4)
+// of block t / 4 of the tile; they start at bit 168 s = 32 (5 s) + 8 s of the
+// block, so the lane reads the block's words 5s .. 5s+5 and shifts the 6-word
+// window right by 8 s bits; code q then sits at bit 21 q of the window.  The
+// wave's six word loads together cover the tile's 1344 contiguous bytes.
 template <>
-struct Seg<CB_FRSZ2_21> : FrszBase<21> {
+struct Tile<CB_FRSZ2_21> {
     uint32_t y[6];
-    __device__ __forceinline__ void load(const BasisView& V, int col, int row0) {
+    uint32_t e;
+    uint32_t s;
+    template <bool FULL>
+    __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         const uint32_t* base = reinterpret_cast<const uint32_t*>(V.values + (int64_t)col * V.col_bytes);
-        const int t = (row0 >> 3) & 3;
-        const uint32_t* p = base + (row0 >> 5) * 21 + 5 * t;
+        const int r = tile0 + 8 * lane;
+        const bool live = FULL || r < V.np;
+        const uint32_t* p = base + (int64_t)(r >> 5) * 21 + 5 * (lane & 3);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = p[k];
-        e = V.exps[(int64_t)col * V.exp_stride + (row0 >> 5)];
+        for (int k = 0; k < 6; ++k) y[k] = live ? __builtin_nontemporal_load(p + k) : 0u;
+        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
+        s = 8u * (lane & 3);
     }
-    __device__ __forceinline__ void codes(int row0, uint32_t* c) const {
-        const uint32_t s = (uint32_t)(8 * ((row0 >> 3) & 3));
+    __device__ __forceinline__ void codes(uint32_t* c) const {
         uint32_t z[6];
 #pragma unroll
         for (int k = 0; k < 5; ++k) z[k] = __builtin_amdgcn_alignbit(y[k + 1], y[k], s);
@@ -262,61 +310,64 @@ struct Seg<CB_FRSZ2_21> : FrszBase<21> {
         c[7] = __builtin_amdgcn_alignbit(z[5], z[4], 19);
     }
     __device__ __forceinline__ static double m_of(uint32_t c) { return signed_mag(c & 0xFFFFFu, c << 11); }
-    int row0_;
-    __device__ __forceinline__ void set_row(int row0) { row0_ = row0; }
     __device__ __forceinline__ double dot(const double* w) const {
         uint32_t c[8];
-        codes(row0_, c);
-        double s = 0.0;
+        codes(c);
+        double sum = 0.0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s = fma(m_of(c[q]), w[q], s);
-        return ldexp(s, scale_exp());
+        for (int q = 0; q < 8; ++q) sum = fma(m_of(c[q]), w[q], sum);
+        return ldexp(sum, scale_exp(e, 21));
     }
     __device__ __forceinline__ void axpy(double h, double* acc) const {
         uint32_t c[8];
-        codes(row0_, c);
-        double hs = ldexp(h, scale_exp());
+        codes(c);
+        const double hs = ldexp(h, scale_exp(e, 21));
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = fma(hs, m_of(c[q]), acc[q]);
     }
     __device__ __forceinline__ void decode(double* out) const {
         uint32_t c[8];
-        codes(row0_, c);
-        int se = scale_exp();
+        codes(c);
+        const int se = scale_exp(e, 21);
 #pragma unroll
         for (int q = 0; q < 8; ++q) out[q] = ldexp(m_of(c[q]), se);
     }
 };
 
-// Uniform entry: load a column segment (all formats).
-template <int FMT>
-__device__ __forceinline__ void seg_load(Seg<FMT>& s, const BasisView& V, int col, int row0) {
-    s.load(V, col, row0);
-    if constexpr (FMT == CB_FRSZ2_21) s.set_row(row0);
+// Load U columns of a tile.
+template <int FMT, int U, bool FULL>
+__device__ __forceinline__ void load_tiles(Tile<FMT>* t, const BasisView& V, const int* cols, int tile0,
+                                           int lane) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u].template load<FULL>(V, cols[u], tile0, lane);
 }
 
-// ----------------------------------------------------------------- writing blocks
-// FRSZ2 code of value v inside its 32-lane group (all 32 lanes participate).
-// Returns the code; *E receives the block's stored exponent field.
+// ----------------------------------------------------------------- writing tiles
+// FRSZ2 code of v with block exponent field E (Section III-A steps 2-5).
 template <int L>
-__device__ __forceinline__ uint32_t frsz2_encode_lane(double v, uint32_t* Eout) {
-    uint32_t hi = hi32(v), lo = lo32(v);
-    uint32_t s = hi >> 31;
-    uint32_t e = (hi >> 20) & 0x7FFu;
-    // step 1: block maximum of the exponent fields over the 32-lane group
-    uint32_t E = e;
-#pragma unroll
-    for (int off = 16; off >= 1; off >>= 1) E = max(E, (uint32_t)__shfl_xor((int)E, off, 32));
-    *Eout = E;
-    uint32_t Eeff = E ? E : 1u;
-    uint32_t eeff = e ? e : 1u;
+__device__ __forceinline__ uint32_t frsz2_code(double v, uint32_t E) {
+    const uint32_t hi = hi32(v), lo = lo32(v);
+    const uint32_t e = (hi >> 20) & 0x7FFu;
+    const uint32_t Eeff = E ? E : 1u;
+    const uint32_t eeff = e ? e : 1u;
     // step 2: significand with the leading one made explicit (53 bits)
-    uint64_t sig = ((uint64_t)((hi & 0xFFFFFu) | (e ? 0x100000u : 0u)) << 32) | lo;
-    // steps 3 and 5: align to E (shift by k = E - e) and keep l-1 bits
-    uint32_t drop = (uint32_t)(54 - L) + (Eeff - eeff);
-    uint32_t M = drop >= 53u ? 0u : (uint32_t)(sig >> drop);
-    // step 4: sign to the left of the significand
-    return (s << (L - 1)) | M;
+    const uint64_t sig = ((uint64_t)((hi & 0xFFFFFu) | (e ? 0x100000u : 0u)) << 32) | lo;
+    // steps 3 and 5: align to E (shift right by k = E - e) and keep l-1 bits
+    const uint32_t drop = (uint32_t)(54 - L) + (Eeff - eeff);
+    const uint32_t M = drop >= 53u ? 0u : (uint32_t)(sig >> drop);
+    // step 4: the sign to the left of the significand
+    return ((hi >> 31) << (L - 1)) | M;
+}
+
+__device__ __forceinline__ uint32_t exp_field(double v) { return (hi32(v) >> 20) & 0x7FFu; }
+
+// max over lane groups of 2^LOG lanes (LOG <= 3) with DPP moves inside rows
+template <int LOG>
+__device__ __forceinline__ uint32_t group_max(uint32_t x) {
+    if constexpr (LOG >= 1) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));
+    if constexpr (LOG >= 2) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));
+    if constexpr (LOG >= 3) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false));
+    return x;
 }
 
 }  // namespace dev

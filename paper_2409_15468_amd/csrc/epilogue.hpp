@@ -1,0 +1,223 @@
+// Second reduction stage and the solver's per-step decisions, run by the
+// last workgroup of the kernel that produced the per-workgroup partial sums.
+//
+// Every workgroup writes its partials, then takes a ticket from a device
+// counter; the workgroup that draws the last ticket sums the partials in
+// workgroup-index order (so the result does not depend on which workgroup
+// finished last), stores or applies the sums, and resets the counter for the
+// next launch on the stream.  Partials are written and read with device-scope
+// (agent) relaxed atomic accesses, which are coherent across the XCDs' L2
+// caches, and each thread waits for its stores to complete before the ticket
+// is drawn; no cache-wide writeback or invalidate is needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cb_internal.hpp"
+#include "reduce.hpp"
+
+namespace cb {
+
+// Device-resident control block of a solve (one per workspace).
+struct State {
+    double nb, tol_abs, eta;
+    double beta;       // ||r|| at the start of the cycle
+    double r2;         // ||r||^2 (or ||b||^2 at init)
+    double om2;        // ||A v||^2
+    double hn2;        // ||w||^2 after a Gram-Schmidt pass
+    double hn;         // h_{j+1,j}: the divisor of the next basis vector
+    double omega;      // ||A v||
+    double omega_pre;  // ||w|| before the re-orthogonalisation pass
+    double gabs;       // |g_{j+1}|
+    double rel;        // last explicit relative residual
+    double basis_bytes;
+    int32_t active;    // 1 while the current cycle continues
+    int32_t reorth;    // 1 while the current step needs the second pass
+    int32_t steps;     // steps taken in the current cycle
+    int32_t prev_steps;
+    int32_t iters, reorths, breakdowns, converged;
+    int32_t stop, status, cycles, max_iters;
+    int32_t literal, pad0, pad1, pad2;
+};
+
+enum EpiMode : int {
+    EPI_STORE = 0,          // out[c] = sum
+    EPI_STEP_CHECK = 1,     // first Gram-Schmidt pass done: norm -> step 7 test
+    EPI_REORTH_PROJECT = 2, // u = sum; h += u
+    EPI_REORTH_FINISH = 3,  // second pass done: norm -> breakdown test, Givens
+};
+
+struct Epi {
+    int mode;
+    int ncols;             // sums to form
+    int G;                 // partials per column (column stride of `partials`)
+    double* out;           // EPI_STORE / EPI_REORTH_PROJECT (u)
+    unsigned* counter;
+    // solver context (modes 1-3)
+    State* st;
+    double* H;             // column-major (m+1) x m
+    double* cs;
+    double* sn;
+    double* g;
+    double* hist;
+    int j;                 // Arnoldi step (0-based): column j of H
+    int m;
+    double col_bytes;
+};
+
+namespace dev {
+
+__device__ __forceinline__ void store_partial(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_partial(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum partials[c * G + g] over g for c < ncols into sums[c] (LDS, ncols <= 256)
+// or out; two threads per column, each over half of the workgroups in order.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int G, int c0, int nc,
+                                                double* lds2) {
+    const int half = (G + 1) / 2;
+    for (int idx = threadIdx.x; idx < 2 * nc; idx += blockDim.x) {
+        const int c = c0 + (idx >> 1);
+        const int lo = (idx & 1) ? half : 0;
+        const int hi = (idx & 1) ? G : half;
+        const double* p = partials + (int64_t)c * G;
+        double s = 0.0;
+        for (int k = lo; k < hi; ++k) s += load_partial(p + k);
+        lds2[idx] = s;
+    }
+}
+
+// Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
+// Givens rotations, implicit residual, end-of-cycle decision.  Called by all
+// threads of one workgroup; H column j, cs and sn are staged in LDS.
+__device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, double* lds) {
+    State& s = *e.st;
+    const int j = e.j;
+    double* h = e.H + (int64_t)j * (e.m + 1);
+    double* lh = lds;                // j + 2 entries
+    double* lc = lds + (j + 2);      // j entries
+    double* ls = lc + j;             // j entries
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) lh[i] = h[i];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        lc[i] = e.cs[i];
+        ls[i] = e.sn[i];
+    }
+    __syncthreads();
+    if (!isfinite(hn)) {
+        if (threadIdx.x == 0) {
+            s.active = 0;
+            s.stop = 1;
+            s.status = CB_ERR_NONFINITE;
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        if (hn == 0.0) breakdown = 1;
+        lh[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            const double a = lh[i], b = lh[i + 1];
+            lh[i] = lc[i] * a + ls[i] * b;
+            lh[i + 1] = -ls[i] * a + lc[i] * b;
+        }
+        const double rho = sqrt(lh[j] * lh[j] + hn * hn);
+        const double c = lh[j] / rho, sn = hn / rho;
+        e.cs[j] = c;
+        e.sn[j] = sn;
+        lh[j] = rho;
+        lh[j + 1] = 0.0;
+        e.g[j + 1] = -sn * e.g[j];
+        e.g[j] = c * e.g[j];
+        s.iters += 1;
+        s.steps = j + 1;
+        s.gabs = fabs(e.g[j + 1]);
+        e.hist[j] = s.gabs;
+        if (s.gabs <= s.tol_abs || breakdown || s.iters >= s.max_iters || j + 1 == e.m) {
+            s.active = 0;
+            s.breakdowns += breakdown;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) h[i] = lh[i];
+}
+
+// LDS (doubles) the epilogue needs: the column sums, or H column j with the
+// rotations for the Givens update of the solver modes.
+constexpr int kEpiLds = 3 * (kMaxRestart + 2) > 512 ? 3 * (kMaxRestart + 2) : 512;
+
+// Run by every workgroup of the launch after its partials are written
+// (all threads; blockDim.x == 256).
+__device__ __forceinline__ void epilogue(const Epi& e, const double* __restrict__ partials, double* lds) {
+    __shared__ int is_last;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned total = gridDim.x * gridDim.y;
+        is_last = __hip_atomic_fetch_add(e.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                  total - 1;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    if ((e.mode == EPI_STORE && e.ncols > 1) || e.mode == EPI_REORTH_PROJECT) {
+        for (int c0 = 0; c0 < e.ncols; c0 += 256) {
+            const int nc = min(256, e.ncols - c0);
+            reduce_partials(partials, e.G, c0, nc, lds);
+            __syncthreads();
+            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+                const double u = lds[2 * i] + lds[2 * i + 1];
+                e.out[c0 + i] = u;
+                if (e.mode == EPI_REORTH_PROJECT) e.H[(int64_t)e.j * (e.m + 1) + c0 + i] += u;
+            }
+            __syncthreads();
+        }
+    } else {
+        // one sum (a squared norm): every thread sums its share, then a block sum
+        double t = 0.0;
+        for (int k = threadIdx.x; k < e.G; k += blockDim.x) t += load_partial(partials + k);
+        t = block_sum<256>(t);
+        if (e.mode == EPI_STORE) {
+            if (threadIdx.x == 0) {
+                e.out[0] = t;
+                *e.counter = 0u;
+            }
+            return;
+        }
+        __shared__ int do_finish, bd;
+        __shared__ double hn_s;
+        if (threadIdx.x == 0) {
+            State& s = *e.st;
+            do_finish = 0;
+            bd = 0;
+            s.hn2 = t;
+            s.hn = sqrt(t);
+            hn_s = s.hn;
+            if (e.mode == EPI_STEP_CHECK) {
+                s.omega = sqrt(s.om2);
+                s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
+                if (s.hn < s.eta * s.omega) {
+                    s.reorth = 1;  // steps 7-11 follow
+                    s.omega_pre = s.hn;
+                } else {
+                    s.reorth = 0;
+                    do_finish = 1;
+                }
+            } else {  // EPI_REORTH_FINISH
+                s.reorths += 1;
+                s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
+                bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
+                s.reorth = 0;
+                do_finish = 1;
+            }
+        }
+        __syncthreads();
+        if (do_finish) finish_step(e, bd, hn_s, lds);
+    }
+    if (threadIdx.x == 0) *e.counter = 0u;
+}
+
+}  // namespace dev
+}  // namespace cb

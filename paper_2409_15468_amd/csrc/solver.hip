@@ -3,47 +3,31 @@
 //
 // Every scalar decision of the method -- the re-orthogonalisation test (step
 // 7), breakdown (step 12), the Givens rotations and the implicit residual
-// (steps 16-17), the end of a cycle -- is taken on the GPU by one-wave kernels
-// that write a control block in device memory.  The host enqueues a whole
-// cycle of m steps without waiting; kernels of steps after the cycle has ended
-// read the control block and return at once.  The host waits once per cycle,
-// after the explicit residual of the restart (step 1 / 18, Eq. 4) has been
-// evaluated, to learn whether to stop.
+// (steps 16-17), the end of a cycle -- is taken on the GPU, by the last
+// workgroup of the kernel whose reduction it needs (epilogue.hpp), and written
+// to a control block in device memory.  A step is six launches: SpMV (+ its
+// norm), projection (+ h), update (+ norm and step 7 test), the second
+// projection and update when step 7 asks for them (+ breakdown test and Givens
+// rotation), and the normalise-and-store of the next basis vector.  The host
+// enqueues a whole cycle of m steps without waiting; kernels of steps after
+// the cycle has ended read the control block and return at once.  The host
+// waits once per cycle, after the explicit residual of the restart (step 1 /
+// 18, Eq. 4) has been evaluated, to learn whether to stop.
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
 
 #include "cb_internal.hpp"
+#include "epilogue.hpp"
 #include "reduce.hpp"
 
 namespace cb {
 
 using namespace dev;
 
-struct State {
-    double nb, tol_abs, eta;
-    double beta;       // ||r|| at the start of the cycle
-    double r2;         // reduction target: ||r||^2 (or ||b||^2 at init)
-    double om2;        // ||A v||^2
-    double hn2;        // ||w||^2 after a Gram-Schmidt pass
-    double hn;         // h_{j+1,j}: the divisor of the next basis vector
-    double omega;      // ||A v||
-    double omega_pre;  // ||w|| before the re-orthogonalisation pass
-    double gabs;       // |g_{j+1}|
-    double rel;        // last explicit relative residual
-    double basis_bytes;
-    int32_t active;    // 1 while the current cycle continues
-    int32_t reorth;    // 1 while the current step needs the second pass
-    int32_t steps;     // steps taken in the current cycle
-    int32_t prev_steps;
-    int32_t iters, reorths, breakdowns, converged;
-    int32_t stop, status, cycles, max_iters;
-    int32_t literal, pad0, pad1, pad2;
-};
-
 struct Layout {
-    int64_t state, flag, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, total;
+    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, total;
 };
 
 static int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -54,6 +38,7 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     auto take = [&](int64_t bytes) { int64_t o = off; off += al(bytes); return o; };
     L.state = take(sizeof(State));
     L.flag = take(sizeof(int32_t));
+    L.counter = take(sizeof(unsigned));
     L.H = take((int64_t)(m + 1) * m * 8);
     L.cs = take((int64_t)m * 8);
     L.sn = take((int64_t)m * 8);
@@ -85,7 +70,8 @@ __global__ void k_sumsq(const double* __restrict__ x, int n, double* __restrict_
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_init(State* st, int32_t* flag, double tol, double eta, int max_iters, int literal) {
+__global__ void k_init(State* st, int32_t* flag, unsigned* counter, double tol, double eta, int max_iters,
+                       int literal) {
     if (threadIdx.x != 0) return;
     State z = {};
     z.nb = sqrt(st->r2);
@@ -106,6 +92,7 @@ __global__ void k_init(State* st, int32_t* flag, double tol, double eta, int max
     }
     *st = z;
     *flag = 0;
+    *counter = 0u;
 }
 
 // Step 1 / 18: beta = ||b - A x|| and the stop test of Eq. 4.
@@ -141,88 +128,27 @@ __global__ void k_cycle_begin(State* st, const int32_t* flag, double* g, int m) 
         for (int i = t; i <= m; i += blockDim.x) g[i] = i == 0 ? st->beta : 0.0;
 }
 
-// Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
-// Givens rotations, implicit residual, end-of-cycle decision.
-__device__ void finish_step(State& s, double* H, double* cs, double* sn, double* g,
-                            double* hist, int j, int m, int breakdown) {
-    double hn = s.hn;
-    if (!isfinite(hn)) {
-        s.active = 0;
-        s.stop = 1;
-        s.status = CB_ERR_NONFINITE;
-        return;
-    }
-    if (hn == 0.0) breakdown = 1;
-    double* h = H + (int64_t)j * (m + 1);
-    h[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        double a = h[i], b = h[i + 1];
-        h[i] = cs[i] * a + sn[i] * b;
-        h[i + 1] = -sn[i] * a + cs[i] * b;
-    }
-    double rho = sqrt(h[j] * h[j] + hn * hn);
-    cs[j] = h[j] / rho;
-    sn[j] = hn / rho;
-    h[j] = rho;
-    h[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    s.iters += 1;
-    s.steps = j + 1;
-    s.gabs = fabs(g[j + 1]);
-    hist[j] = s.gabs;
-    if (s.gabs <= s.tol_abs || breakdown || s.iters >= s.max_iters || j + 1 == m) {
-        s.active = 0;
-        s.breakdowns += breakdown;
-    }
-}
-
-// After the first Gram-Schmidt pass: omega, h_{j+1,j} and the step 7 test.
-__global__ void k_step_check(State* st, double* H, double* cs, double* sn, double* g,
-                             double* hist, int j, int m, double col_bytes) {
-    if (threadIdx.x != 0) return;
-    State& s = *st;
-    if (!s.active) return;
-    s.omega = sqrt(s.om2);
-    s.hn = sqrt(s.hn2);
-    s.basis_bytes += 2.0 * (j + 1) * col_bytes;
-    if (s.hn < s.eta * s.omega) {
-        s.reorth = 1;
-        s.omega_pre = s.hn;
-    } else {
-        s.reorth = 0;
-        finish_step(s, H, cs, sn, g, hist, j, m, 0);
-    }
-}
-
-// After the re-orthogonalisation pass (steps 8-11): h += u, new norm, breakdown.
-__global__ void k_step_finish(State* st, double* H, const double* u, double* cs, double* sn,
-                              double* g, double* hist, int j, int m, double col_bytes) {
-    State& s = *st;
-    if (!s.active || !s.reorth) return;
-    double* h = H + (int64_t)j * (m + 1);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] += u[i];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    s.hn = sqrt(s.hn2);
-    s.reorths += 1;
-    s.basis_bytes += 2.0 * (j + 1) * col_bytes;
-    int bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
-    s.reorth = 0;
-    finish_step(s, H, cs, sn, g, hist, j, m, bd);
-}
-
-// Step 17: back-substitution R y = g over the cycle's steps.
-__global__ void k_backsolve(State* st, const double* H, const double* g, double* y, int m,
-                            double col_bytes) {
-    if (threadIdx.x != 0) return;
+// Step 17: back-substitution R y = g over the cycle's steps, by columns: y_i
+// is fixed, then column i of R is removed from the right-hand side in parallel.
+__global__ __launch_bounds__(256) void k_backsolve(State* st, const double* __restrict__ H,
+                                                   const double* __restrict__ g, double* __restrict__ y,
+                                                   int m, double col_bytes) {
+    __shared__ double rhs[kMaxRestart];
+    __shared__ double yi;
     const int k1 = st->steps;
+    for (int i = threadIdx.x; i < k1; i += blockDim.x) rhs[i] = g[i];
+    __syncthreads();
     for (int i = k1 - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int k = i + 1; k < k1; ++k) s -= H[(int64_t)k * (m + 1) + i] * y[k];
-        y[i] = s / H[(int64_t)i * (m + 1) + i];
+        const double* col = H + (int64_t)i * (m + 1);
+        if (threadIdx.x == 0) {
+            yi = rhs[i] / col[i];
+            y[i] = yi;
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < i; r += blockDim.x) rhs[r] -= col[r] * yi;
+        __syncthreads();
     }
-    st->basis_bytes += (double)k1 * col_bytes;
+    if (threadIdx.x == 0) st->basis_bytes += (double)k1 * col_bytes;
 }
 
 __global__ void k_axpy(double* __restrict__ x, const double* __restrict__ d, int n) {
@@ -278,6 +204,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
 
     State* st = W.at<State>(W.L.state);
     int32_t* flag = W.at<int32_t>(W.L.flag);
+    unsigned* counter = W.at<unsigned>(W.L.counter);
     double* H = W.at<double>(W.L.H);
     double* cs = W.at<double>(W.L.cs);
     double* sn = W.at<double>(W.L.sn);
@@ -291,11 +218,25 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     cb_basis V{fmt, n, m + 1, 0, W.base + W.L.vals,
                frsz2_bits_of(fmt) ? W.at<uint32_t>(W.L.exps) : nullptr};
     const double cbytes = (double)column_bytes(fmt, n);
-    const int Gb = row_groups(n);
-    const int Gs = spmv_groups(n, A.nnz);
     int* active = &st->active;
     int* reorth = &st->reorth;
     int* steps = &st->steps;
+
+    // epilogue templates: a plain sum into the control block, and the solver
+    // step logic (column j filled in per launch)
+    Epi sum_e{};
+    sum_e.mode = EPI_STORE;
+    sum_e.counter = counter;
+    Epi step_e{};
+    step_e.counter = counter;
+    step_e.st = st;
+    step_e.H = H;
+    step_e.cs = cs;
+    step_e.sn = sn;
+    step_e.g = g;
+    step_e.hist = hist;
+    step_e.m = m;
+    step_e.col_bytes = cbytes;
 
     State* hs = static_cast<State*>(g_pinned.get(sizeof(State) + (size_t)m * 8));
     if (!hs) return fail(CB_ERR_HIP, "hipHostMalloc failed");
@@ -304,7 +245,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
 
     // ||b||, tolerances, counters
     enqueue_sumsq(b, n, part, &st->r2, s);
-    k_init<<<1, 64, 0, s>>>(st, flag, tol, eta, max_iters, literal);
+    k_init<<<1, 64, 0, s>>>(st, flag, counter, tol, eta, max_iters, literal);
     CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
     CB_HIP(hipStreamSynchronize(s));
     if (hs->stop) {
@@ -314,8 +255,9 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
         bool capped = false;
         for (;;) {
             // restart: explicit residual into w, beta, stop test
-            launch_spmv(A, x, b, w, part, 1, nullptr, s);
-            launch_reduce(part, Gs, 1, &st->r2, 0, nullptr, s);
+            Epi e = sum_e;
+            e.out = &st->r2;
+            launch_spmv(A, x, b, w, part, 1, nullptr, e, s);
             k_cycle_begin<<<1, 64, 0, s>>>(st, flag, g, m);
             CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
             if (cycles > 0) CB_HIP(hipMemcpyAsync(hh, hist, (size_t)m * 8, hipMemcpyDeviceToHost, s));
@@ -328,22 +270,30 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
             // v_1 = r / beta, V_1 = Q(v_1)
             launch_store(fmt, V, 0, w, &st->beta, v, flag, active, s);
             for (int j = 0; j < m; ++j) {
-                launch_spmv(A, v, nullptr, w, part, 0, active, s);
-                launch_reduce(part, Gs, 1, &st->om2, 0, active, s);
-                launch_project(fmt, V, j + 1, w, part, active, s);
-                launch_reduce(part, Gb, j + 1, H + (int64_t)j * (m + 1), 0, active, s);
-                launch_subtract(fmt, V, j + 1, nullptr, H + (int64_t)j * (m + 1), w, part, active, -1, s);
-                launch_reduce(part, Gb, 1, &st->hn2, 0, active, s);
-                k_step_check<<<1, 64, 0, s>>>(st, H, cs, sn, g, hist, j, m, cbytes);
-                launch_project(fmt, V, j + 1, w, part, reorth, s);
-                launch_reduce(part, Gb, j + 1, u, 0, reorth, s);
-                launch_subtract(fmt, V, j + 1, nullptr, u, w, part, reorth, -1, s);
-                launch_reduce(part, Gb, 1, &st->hn2, 0, reorth, s);
-                k_step_finish<<<1, 64, 0, s>>>(st, H, u, cs, sn, g, hist, j, m, cbytes);
+                double* hcol = H + (int64_t)j * (m + 1);
+                Epi eo = sum_e;          // omega^2 = ||A v||^2
+                eo.out = &st->om2;
+                launch_spmv(A, v, nullptr, w, part, 0, active, eo, s);
+                Epi eh = sum_e;          // h_{1:j+1,j}
+                eh.out = hcol;
+                launch_project(fmt, V, j + 1, w, part, active, eh, s);
+                Epi ec = step_e;         // ||w||, step 7 test, maybe Givens
+                ec.mode = EPI_STEP_CHECK;
+                ec.j = j;
+                launch_subtract(fmt, V, j + 1, nullptr, hcol, w, part, active, -1, ec, s);
+                Epi eu = step_e;         // u = V^T w, h += u
+                eu.mode = EPI_REORTH_PROJECT;
+                eu.out = u;
+                eu.j = j;
+                launch_project(fmt, V, j + 1, w, part, reorth, eu, s);
+                Epi ef = step_e;         // ||w||, breakdown test, Givens
+                ef.mode = EPI_REORTH_FINISH;
+                ef.j = j;
+                launch_subtract(fmt, V, j + 1, nullptr, u, w, part, reorth, -1, ef, s);
                 if (j + 1 < m) launch_store(fmt, V, j + 1, w, &st->hn, v, flag, active, s);
             }
-            k_backsolve<<<1, 64, 0, s>>>(st, H, g, y, m, cbytes);
-            launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, s);
+            k_backsolve<<<1, 256, 0, s>>>(st, H, g, y, m, cbytes);
+            launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, Epi{}, s);
             CB_HIP(hipGetLastError());
             ++cycles;
             if (max_cycles > 0 && cycles >= max_cycles) {
@@ -385,7 +335,8 @@ static int check_solve_args(const cb_csr* A, const double* b, const double* x, i
     if (!A || !b || !x) return fail(CB_ERR_INVALID_ARG, "NULL argument");
     if (A->n < 1 || A->n > INT32_MAX - 64 || A->nnz < 0 || !A->row_ptr || (A->nnz && (!A->col || !A->val)))
         return fail(CB_ERR_INVALID_ARG, "bad matrix");
-    if (m < 1 || m > 4096) return fail(CB_ERR_INVALID_ARG, "restart m=%d out of range [1, 4096]", m);
+    if (m < 1 || m > kMaxRestart)
+        return fail(CB_ERR_INVALID_ARG, "restart m=%d out of range [1, %d]", m, kMaxRestart);
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(CB_ERR_INVALID_ARG, "tol must be positive");
     if (!valid_format(format)) return fail(CB_ERR_INVALID_ARG, "unknown basis format %d", format);
     return CB_OK;
@@ -448,7 +399,6 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
     double* d = reinterpret_cast<double*>(W.base + W.L.total + vec);
     double* scal = reinterpret_cast<double*>(W.base + W.L.total + 2 * vec);
     double* part = W.at<double>(W.L.part);
-    const int Gs = spmv_groups(n, A->nnz);
     double* hv = static_cast<double*>(g_pinned.get(sizeof(State) + (size_t)m * 8 + 64));
     int status = CB_ERR_NOT_CONVERGED;
     cb_result acc;
@@ -469,8 +419,12 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
         goto done;
     }
     for (;;) {
-        launch_spmv(*A, x, b, r, part, 1, nullptr, s);
-        launch_reduce(part, Gs, 1, scal, 0, nullptr, s);
+        Epi e{};
+        e.mode = EPI_STORE;
+        e.out = scal;
+        e.counter = W.at<unsigned>(W.L.counter);
+        launch_zero_counter(e.counter, s);
+        launch_spmv(*A, x, b, r, part, 1, nullptr, e, s);
         if (hipMemcpyAsync(hv, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { status = fail(CB_ERR_HIP, "copy failed"); goto done; }
         const double rn = std::sqrt(hv[0]);

@@ -46,7 +46,11 @@ def test_size_queries_match_storage_definitions():
         for bits in (16, 21, 32):
             assert cb.frsz2_value_words(n, bits) == bits * ((n + 31) // 32)
         for fmt in oracle.FORMATS:
-            assert cb.cb_basis_column_bytes(fmt, n) == oracle.col_bytes(fmt, n)
+            stride = cb.cb_basis_column_bytes(fmt, n)
+            data = oracle.col_bytes(fmt, n)
+            assert stride % 256 == 0 and data <= stride < data + 256
+            V = cb.Basis(cb.FORMATS[fmt], n, 1, None, None)
+            assert V.column_data_bytes() == data
             ew = cb.cb_basis_exponent_words(fmt, n)
             assert ew == ((n + 31) // 32 if fmt.startswith("frsz2") else 0)
     assert cb.frsz2_value_words(10, 17) == -1

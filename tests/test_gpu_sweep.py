@@ -1,0 +1,51 @@
+"""Full-size basis-format sweep on the GPU: 3D convection-diffusion on a
+100^3 grid (n = 10^6, 6.94e6 nonzeros), GMRES(100), tol 1e-10, every basis
+format, in the configuration the benchmark times.  Each solve must reach the
+stated relative residual (recomputed on the host), take within 2% of the
+oracle's iteration count (tests/golden/sweep_oracle_<format>.json, written by
+make_sweep_reference.py from the oracle), and its solution is compared with
+the oracle's at the 4096 stored sample rows."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2409_15468_amd as cb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+FORMATS = ["float64", "float32", "float16", "frsz2_16", "frsz2_21", "frsz2_32"]
+
+
+@pytest.fixture(scope="module")
+def system():
+    s = synth.sweep_3d(N=100, seed=1)
+    A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    b = torch.from_numpy(s.b).cuda()
+    ws = torch.empty(cb.cbgmres_workspace_bytes(s.A.n, 100, "float64") // 8 + 1, dtype=torch.float64,
+                     device="cuda")
+    return s, A, b, ws
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_sweep_format(system, fmt):
+    s, A, b, ws = system
+    with open(os.path.join(GOLDEN, f"sweep_oracle_{fmt}.json")) as f:
+        ref = json.load(f)
+    x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    res, _ = cb.cbgmres_solve(A, b, x, 100, 1e-10, fmt, workspace=ws)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    rel = np.linalg.norm(s.b - s.A.scipy() @ xh) / np.linalg.norm(s.b)
+    rows = np.array(ref["sample_rows"])
+    xs = np.array(ref["x_sample"])
+    err = np.linalg.norm(xh[rows] - xs) / np.linalg.norm(xs)
+    print(f"{fmt}: gpu {res['iterations']} iters / {res['restarts']} cycles in {res['seconds'] * 1e3:.1f} ms, "
+          f"oracle {ref['iterations']}; rel {rel:.3e}; sampled error vs oracle x {err:.2e}")
+    assert res["status"] == 0 and res["converged"]
+    assert rel <= 1e-10 * (1 + 1e-6)
+    assert abs(res["iterations"] - ref["iterations"]) <= max(1, int(np.ceil(0.02 * ref["iterations"])))
+    assert err < 1e-6
