@@ -131,14 +131,14 @@ int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double
 int cb_basis_load(const cb_basis* V, int32_t col, double* x, void* stream);
 
 /* Bytes of reduction workspace needed by the primitives below for n rows and
- * up to ncols columns: a 256-byte header (a completion counter the call
- * resets itself) followed by per-workgroup partial sums.  Calls that share a
+ * up to ncols columns: an 8 KB header (ticket counters that the call clears
+ * itself) followed by per-workgroup partial sums.  Calls that share a
  * workspace must run in stream order. */
 int64_t cb_reduce_workspace_bytes(int32_t n, int32_t ncols);
 
 /* Classical Gram-Schmidt projection with decompression fused into the read
  * (Fig. 1 step 5, first half): h[i] = sum_k D(v_i)[k] * w[k] for
- * i = 0..j-1, all against the same w.  h: device float64[j].  The sum over k
+ * i = 0..j-1 (1 <= j <= 513), all against the same w.  h: device float64[j].  The sum over k
  * runs in a fixed order that depends on n only (deterministic).
  * Asynchronous. */
 int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, void* work,
@@ -168,9 +168,8 @@ typedef struct cb_csr {
 } cb_csr;
 
 /* y = A x (Fig. 1 step 3, M = I) and, if norm2 != NULL, *norm2 = ||y||^2
- * (step 4); the norm needs work_bytes >= 256 + 8 * (number of row groups),
- * 256 + 8 * (n + 1) always suffices.  Column indices must lie in [0, n).
- * Asynchronous. */
+ * (step 4); the norm needs a device workspace of 8 * (n + 1) bytes.  Column
+ * indices must lie in [0, n).  Asynchronous. */
 int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
             size_t work_bytes, void* stream);
 

@@ -331,7 +331,7 @@ class DeviceCSR:
 
 def _spmv_work(A: DeviceCSR, device):
     import torch
-    nbytes = 256 + 8 * (A.n + 1)
+    nbytes = 8 * (A.n + 1)
     return torch.empty(nbytes // 8, dtype=torch.float64, device=device), nbytes
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbgmres.so")
 SOURCES = ["api.hip", "basis.hip", "spmv.hip", "solver.hip", "server.cpp"]
-HEADERS = ["cb_internal.hpp", "codec.hpp", "reduce.hpp"]
+HEADERS = ["cb_internal.hpp", "codec.hpp", "reduce.hpp", "epilogue.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

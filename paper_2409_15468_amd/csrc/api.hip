@@ -47,12 +47,12 @@ int64_t column_bytes(int f, int64_t n) {
 
 int64_t exponent_words(int f, int64_t n) { return frsz2_bits_of(f) ? nblocks(n) : 0; }
 
-// Workspace of the primitives: a 256-byte header holding the completion
-// counter of the last-workgroup reduction, then the partial sums.
+// Workspace of the primitives: a header holding the ticket counters of the
+// last-workgroup reduction, then the partial sums.
 int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz) {
-    int64_t a = (int64_t)row_groups(n) * (ncols > 0 ? ncols : 1);
+    int64_t a = (int64_t)project_groups(n) * (ncols > 0 ? ncols : 1);
     int64_t b = nnz > 0 ? spmv_groups(n, nnz) : 0;
-    return 256 + 8 * (a > b ? a : b);
+    return kCounterBytes + 8 * (a > b ? a : b);
 }
 
 static Epi store_epi(double* out, void* work) {
@@ -63,7 +63,7 @@ static Epi store_epi(double* out, void* work) {
     return e;
 }
 static double* partials_of(void* work) {
-    return reinterpret_cast<double*>(static_cast<unsigned char*>(work) + 256);
+    return reinterpret_cast<double*>(static_cast<unsigned char*>(work) + kCounterBytes);
 }
 
 static bool bad_n(int64_t n) { return n < 1 || n > (int64_t)INT32_MAX - 64; }
@@ -174,6 +174,8 @@ int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, voi
                    size_t work_bytes, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !w || !h || !work) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (j > kMaxRestart + 1)
+        return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     if ((int64_t)work_bytes < reduce_workspace_bytes(V->n, j, 0))
         return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", work_bytes,
                     (long long)reduce_workspace_bytes(V->n, j, 0));
@@ -219,12 +221,14 @@ int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* wo
             size_t work_bytes, void* stream) {
     if (int st = check_csr(A)) return st;
     if (!x || !y) return fail(CB_ERR_INVALID_ARG, "NULL vector");
-    const int64_t need = 256 + 8 * (int64_t)spmv_groups(A->n, A->nnz);
+    const int G = spmv_groups(A->n, A->nnz);
+    const int64_t need = 8 * (int64_t)G;
     if (norm2 && (!work || (int64_t)work_bytes < need))
         return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
     hipStream_t s = (hipStream_t)stream;
-    if (norm2) launch_zero_counter(static_cast<unsigned*>(work), s);
-    launch_spmv(*A, x, nullptr, y, norm2 ? partials_of(work) : nullptr, 0, nullptr, store_epi(norm2, work), s);
+    double* part = norm2 ? static_cast<double*>(work) : nullptr;
+    launch_spmv(*A, x, nullptr, y, part, 0, nullptr, s);
+    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }
@@ -233,12 +237,14 @@ int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, do
                 void* work, size_t work_bytes, void* stream) {
     if (int st = check_csr(A)) return st;
     if (!x || !r || !b) return fail(CB_ERR_INVALID_ARG, "NULL vector");
-    const int64_t need = 256 + 8 * (int64_t)spmv_groups(A->n, A->nnz);
+    const int G = spmv_groups(A->n, A->nnz);
+    const int64_t need = 8 * (int64_t)G;
     if (norm2 && (!work || (int64_t)work_bytes < need))
         return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
     hipStream_t s = (hipStream_t)stream;
-    if (norm2) launch_zero_counter(static_cast<unsigned*>(work), s);
-    launch_spmv(*A, x, b, r, norm2 ? partials_of(work) : nullptr, 1, nullptr, store_epi(norm2, work), s);
+    double* part = norm2 ? static_cast<double*>(work) : nullptr;
+    launch_spmv(*A, x, b, r, part, 1, nullptr, s);
+    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }

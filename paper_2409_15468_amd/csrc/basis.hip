@@ -142,8 +142,8 @@ __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double*
     const int tile0 = blockIdx.x * kRowsPerWG + wave * kTile;
     Tile<FMT> t[1];
     const int cols[1] = {col};
-    if (tile0 + kTile <= V.np) load_tiles<FMT, 1, true>(t, V, cols, tile0, lane);
-    else load_tiles<FMT, 1, false>(t, V, cols, tile0, lane);
+    if (tile0 + kTile <= V.np) load_tiles<FMT, 1, kFull | kStream>(t, V, cols, tile0, lane);
+    else load_tiles<FMT, 1, kStream>(t, V, cols, tile0, lane);
     double out[8];
     t[0].decode(out);
     store_rows<FMT>(x, tile0, lane, V.n, out);
@@ -151,16 +151,16 @@ __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double*
 
 // ----------------------------------------------------------------- CGS projection
 // One wave's columns [c0, c1) of its tile, 8 at a time; the wave's sums for
-// column c land in red[c - c0].  The loads of the next 8 columns are issued
+// column c are added to red[c - c0].  The loads of the next 8 columns are issued
 // before the current 8 are reduced across the wave.
-template <int FMT, bool FULL>
+template <int FMT, int LM>
 __device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1, int tile0, int lane,
                                              const double* wv, double* red) {
     Tile<FMT> t[8];
     int cols[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) cols[u] = min(c0 + u, c1 - 1);
-    load_tiles<FMT, 8, FULL>(t, V, cols, tile0, lane);
+    load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
     for (int c = c0; c < c1; c += 8) {
         double p[8];
 #pragma unroll
@@ -168,32 +168,47 @@ __device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1,
         if (c + 8 < c1) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) cols[u] = min(c + 8 + u, c1 - 1);
-            load_tiles<FMT, 8, FULL>(t, V, cols, tile0, lane);
+            load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
         }
         const double sum = wave_sum8(p);  // lane 8u holds column c + u
-        if ((lane & 7) == 0 && c + (lane >> 3) < c1) red[c + (lane >> 3) - c0] = sum;
+        if ((lane & 7) == 0 && c + (lane >> 3) < c1) red[c + (lane >> 3) - c0] += sum;
     }
 }
 
-// partials[c * G + g] = sum over the workgroup's rows of D(v_c) * w, c < j;
-// the last workgroup then forms the sums over g (see epilogue.hpp).
+// Workgroup (g, y) takes the row groups g, g + G, g + 2G, ... (2048 rows each;
+// G <= kProjectGroups keeps the partials few) and the columns
+// [y cw, (y+1) cw), and writes partials[c * G + g], its sum of D(v_c) * w:
+// per column the waves accumulate over their row groups in order and the waves
+// are then added in order.  The last workgroup forms the sums over g
+// (epilogue.hpp).  Small n gets several column chunks so that the launch still
+// has enough waves to keep HBM busy.
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
                                                       const double* __restrict__ w,
-                                                      double* __restrict__ partials, int G,
-                                                      const int* __restrict__ guard, Epi e) {
+                                                      double* __restrict__ partials, int G, int cw,
+                                                      int stream, const int* __restrict__ guard, Epi e) {
     if (guard && *guard == 0) return;
-    __shared__ double red[kThreads / 64][kColChunk];
+    __shared__ double red[kThreads / 64][kMaxRestart + 1];
     __shared__ double elds[kEpiLds];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.x;
-    const int c0 = blockIdx.y * kColChunk;
-    const int c1 = min(j, c0 + kColChunk);
-    const int tile0 = g * kRowsPerWG + wave * kTile;
-    double wv[8];
-    load_rows<FMT>(w, tile0, lane, V.n, wv);
-    if (tile0 + kTile <= V.np) project_tile<FMT, true>(V, c0, c1, tile0, lane, wv, red[wave]);
-    else project_tile<FMT, false>(V, c0, c1, tile0, lane, wv, red[wave]);
+    const int ngroups = row_groups_dev(V.np);
+    const int c0 = blockIdx.y * cw;  // this workgroup's columns [c0, c1)
+    const int c1 = min(j, c0 + cw);
+    for (int i = lane; i < c1 - c0; i += 64) red[wave][i] = 0.0;
+    for (int rg = g; rg < ngroups; rg += G) {
+        const int tile0 = rg * kRowsPerWG + wave * kTile;
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);
+        const bool full = tile0 + kTile <= V.np;
+        if (stream) {
+            if (full) project_tile<FMT, kFull | kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+            else project_tile<FMT, kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+        } else {
+            if (full) project_tile<FMT, kFull>(V, c0, c1, tile0, lane, wv, red[wave]);
+            else project_tile<FMT, 0>(V, c0, c1, tile0, lane, wv, red[wave]);
+        }
+    }
     __syncthreads();
     for (int i = tid; i < c1 - c0; i += kThreads) {
         double s = red[0][i];
@@ -205,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
 }
 
 // ----------------------------------------------------------------- CGS update / x update
-template <int FMT, int U, bool FULL>
+template <int FMT, int U, int LM>
 __device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const double* __restrict__ h,
                                               int tile0, int lane, double* acc) {
     for (int c = 0; c < j; c += U) {
@@ -213,40 +228,53 @@ __device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const d
         int cols[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
-        load_tiles<FMT, U, FULL>(t, V, cols, tile0, lane);
+        load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
 #pragma unroll
         for (int u = 0; u < U; ++u)
             t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
     }
 }
 
-// w[k] += sign * sum_{c<j} h[c] * D(v_c)[k]; partials[g] = sum of w[k]^2 over
-// the workgroup's rows after the update (if partials != NULL).
+// w[k] += sign * sum_{c<j} h[c] * D(v_c)[k] over the row groups g, g + G, ...
+// of workgroup g; partials[g] = sum of w[k]^2 over those rows after the update
+// (row groups in order, then the waves in order), if partials != NULL, and
+// then the epilogue.
 template <int FMT, int U>
 __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const int* __restrict__ jdev,
                                                        const double* __restrict__ h,
                                                        double* __restrict__ w,
-                                                       double* __restrict__ partials, int sign,
+                                                       double* __restrict__ partials, int sign, int stream,
                                                        const int* __restrict__ guard, Epi e) {
     if (guard && *guard == 0) return;
     if (jdev) j = *jdev;
     __shared__ double elds[kEpiLds];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile0 = blockIdx.x * kRowsPerWG + wave * kTile;
-    double acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    if (tile0 + kTile <= V.np) subtract_tile<FMT, U, true>(V, j, h, tile0, lane, acc);
-    else subtract_tile<FMT, U, false>(V, j, h, tile0, lane, acc);
-    double wv[8];
-    load_rows<FMT>(w, tile0, lane, V.n, wv);
+    const int ngroups = row_groups_dev(V.np);
     double nrm = 0.0;
+    for (int rg = blockIdx.x; rg < ngroups; rg += gridDim.x) {
+        const int tile0 = rg * kRowsPerWG + wave * kTile;
+        double acc[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        wv[q] = sign > 0 ? wv[q] + acc[q] : wv[q] - acc[q];
-        nrm = fma(wv[q], wv[q], nrm);  // rows >= n hold 0
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        const bool full = tile0 + kTile <= V.np;
+        if (stream) {
+            if (full) subtract_tile<FMT, U, kFull | kStream>(V, j, h, tile0, lane, acc);
+            else subtract_tile<FMT, U, kStream>(V, j, h, tile0, lane, acc);
+        } else {
+            if (full) subtract_tile<FMT, U, kFull>(V, j, h, tile0, lane, acc);
+            else subtract_tile<FMT, U, 0>(V, j, h, tile0, lane, acc);
+        }
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            wv[q] = sign > 0 ? wv[q] + acc[q] : wv[q] - acc[q];
+            t = fma(wv[q], wv[q], t);  // rows >= n hold 0
+        }
+        nrm += t;
+        store_rows<FMT>(w, tile0, lane, V.n, wv);
     }
-    store_rows<FMT>(w, tile0, lane, V.n, wv);
     if (partials) {
         const double t = block_sum<kThreads>(nrm);
         if (tid == 0) store_partial(partials + blockIdx.x, t);
@@ -282,9 +310,21 @@ __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
     default: { constexpr int F = CB_FRSZ2_32; KERNEL_CALL; break; }          \
     }
 
-__global__ void k_zero(unsigned* __restrict__ c) { *c = 0u; }
+__global__ void k_zero(unsigned* __restrict__ c, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) c[i] = 0u;
+}
 
-void launch_zero_counter(unsigned* counter, hipStream_t s) { k_zero<<<1, 1, 0, s>>>(counter); }
+// Non-temporal basis loads pay off once the columns one pass reads no longer
+// fit in the 256 MB Infinity Cache next to the rest of the working set; below
+// that, the solver's four passes per step over the same columns hit in it.
+static int streams_basis(const BasisView& b, int j) {
+    constexpr int64_t kCacheResident = (int64_t)192 << 20;
+    return (int64_t)j * (b.col_bytes + 4 * b.exp_stride) > kCacheResident;
+}
+
+void launch_zero_counter(unsigned* counter, hipStream_t s) {
+    k_zero<<<1, 256, 0, s>>>(counter, kCounterBytes / 4);
+}
 
 void launch_store(int fmt, const cb_basis& V, int col, const double* w, const double* divisor,
                   double* v_out, int32_t* flag, const int* guard, hipStream_t s) {
@@ -305,23 +345,38 @@ void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s) 
 void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* partials,
                     const int* guard, const Epi& e, hipStream_t s) {
     BasisView b = view_of(V);
-    const int G = row_groups(V.n);
-    dim3 grid((unsigned)G, (unsigned)((j + kColChunk - 1) / kColChunk));
+    const int G = project_groups(V.n);
+    // column chunks (multiples of 8 columns) until the launch has ~8192 waves
+    int chunks = (8192 + 4 * G - 1) / (4 * G);
+    chunks = chunks < 1 ? 1 : chunks;
+    int max_chunks = (j + 15) / 16;
+    if (max_chunks > kMaxTicketWorkgroups / G) max_chunks = kMaxTicketWorkgroups / G;
+    chunks = chunks > max_chunks ? max_chunks : chunks;
+    chunks = chunks < 1 ? 1 : chunks;
+    int cw = (j + chunks - 1) / chunks;
+    cw = (cw + 7) / 8 * 8;
+    chunks = (j + cw - 1) / cw;
+    dim3 grid((unsigned)G, (unsigned)chunks);
     Epi ee = e;
     ee.G = G;
     ee.ncols = j;
-    CB_DISPATCH(fmt, (k_project<F><<<grid, kThreads, 0, s>>>(b, j, w, partials, G, guard, ee)));
+    const int stream = streams_basis(b, j);
+    CB_DISPATCH(fmt, (k_project<F><<<grid, kThreads, 0, s>>>(b, j, w, partials, G, cw, stream, guard, ee)));
 }
 
 void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const double* h,
                      double* w, double* partials, const int* guard, int sign, const Epi& e,
                      hipStream_t s) {
     BasisView b = view_of(V);
-    dim3 grid((unsigned)row_groups(V.n));
+    const int G = project_groups(V.n);
+    dim3 grid((unsigned)G);
     Epi ee = e;
-    ee.G = row_groups(V.n);
+    ee.G = G;
     ee.ncols = 1;
-    CB_DISPATCH(fmt, (k_subtract<F, 4><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials, sign, guard, ee)));
+    // with the count on the device, size the policy for the largest count j
+    const int stream = streams_basis(b, j);
+    CB_DISPATCH(fmt, (k_subtract<F, 4><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials, sign, stream,
+                                                                guard, ee)));
 }
 
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op, const int* guard,

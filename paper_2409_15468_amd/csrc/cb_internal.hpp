@@ -28,12 +28,19 @@ constexpr int kBS = 32;           // FRSZ2 block size (values per shared exponen
 constexpr int kSeg = 8;           // rows per thread in the row-segment kernels
 constexpr int kThreads = 256;     // threads per workgroup in the row kernels
 constexpr int kRowsPerWG = kThreads * kSeg;  // 2048 rows = 64 FRSZ2 blocks
-constexpr int kColChunk = 64;     // basis columns per workgroup (grid.y tiles more)
+constexpr int kCounterBytes = 8192;  // ticket counters of the last-workgroup reductions
+// workgroups one last-workgroup reduction can serve: one 128-byte top counter
+// line plus one line per 32 workgroups
+constexpr int kMaxTicketWorkgroups = (kCounterBytes / 128 - 1) * 32;
 constexpr int kMaxRestart = 512;  // largest restart length m
 
 inline int64_t nblocks(int64_t n) { return (n + kBS - 1) / kBS; }
 inline int64_t padded_rows(int64_t n) { return nblocks(n) * kBS; }
 inline int row_groups(int64_t n) { return (int)((padded_rows(n) + kRowsPerWG - 1) / kRowsPerWG); }
+__host__ __device__ inline int row_groups_dev(int np) { return (np + kRowsPerWG - 1) / kRowsPerWG; }
+// workgroups of the basis kernels: one per row group, at most kProjectGroups
+constexpr int kProjectGroups = 1024;
+inline int project_groups(int64_t n) { int g = row_groups(n); return g < kProjectGroups ? g : kProjectGroups; }
 
 inline bool valid_format(int f) { return f >= CB_F64 && f <= CB_FRSZ2_32; }
 inline int frsz2_bits_of(int f) {
@@ -90,9 +97,9 @@ void launch_zero_counter(unsigned* counter, hipStream_t s);
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op,
                    const int* guard, hipStream_t s);
 // y = A x (mode 0) or y = b - A x (mode 1); with partials != NULL also
-// ||y||^2 per workgroup and the epilogue e on it.
+// ||y||^2 per workgroup (spmv_groups of them, summed by the consumer).
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
-                 int mode, const int* guard, const Epi& e, hipStream_t s);
+                 int mode, const int* guard, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 
 }  // namespace cb

@@ -9,7 +9,9 @@
 // k < 2; float16, frsz2_16 and frsz2_21 lanes own 8t .. 8t+7.  Each such group
 // of rows lies inside one 32-value FRSZ2 block.  frsz2_21 codes straddle words:
 // a lane loads the 6 words that hold its 8 codes.  Basis loads are
-// non-temporal: each pass streams the basis once.
+// non-temporal when the columns a pass reads exceed what the Infinity Cache can
+// keep between passes (the solver re-reads them up to four times per step),
+// ordinary otherwise.
 //
 // FRSZ2 values are never materialised with their scale: a code becomes the
 // exact signed integer +-M (a 32-bit convert and a sign-bit insert), products
@@ -31,10 +33,24 @@ constexpr int kTile = 512;  // rows of a column per wavefront
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint4 ld_stream(const void* p) {
-    u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-    return make_uint4(v.x, v.y, v.z, v.w);
+// 16-byte load; NT: non-temporal (streaming, does not displace cached data)
+template <bool NT>
+__device__ __forceinline__ uint4 ld16(const void* p) {
+    if constexpr (NT) {
+        u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const uint4*>(p);
+    }
 }
+template <bool NT>
+__device__ __forceinline__ uint32_t ld4(const uint32_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+// Load mode of a tile: bit 0 the tile lies wholly inside the column (no row
+// checks), bit 1 non-temporal loads.
+constexpr int kFull = 1, kStream = 2;
 __device__ __forceinline__ uint32_t word_of(const uint4& a, int i) {
     return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? a.z : a.w;
 }
@@ -149,14 +165,15 @@ template <int FMT>
 struct FloatTile {
     using M = Map<FMT>;
     uint4 x[M::NG];
-    template <bool FULL>
+    template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
         constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
 #pragma unroll
         for (int k = 0; k < M::NG; ++k) {
             const int r = tile0 + M::group_row(lane, k);
-            x[k] = (FULL || r < V.np) ? ld_stream(base + (int64_t)r * esz) : make_uint4(0, 0, 0, 0);
+            x[k] = ((LM & kFull) || r < V.np) ? ld16<(LM & kStream) != 0>(base + (int64_t)r * esz)
+                                              : make_uint4(0, 0, 0, 0);
         }
     }
     __device__ __forceinline__ double v(int q) const {
@@ -197,15 +214,15 @@ struct Tile<CB_FRSZ2_32> {
     using M = Map<CB_FRSZ2_32>;
     uint4 x[2];
     uint32_t e[2];
-    template <bool FULL>
+    template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
         const uint32_t* ex = V.exps + (int64_t)col * V.exp_stride;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int r = tile0 + M::group_row(lane, k);
-            const bool live = FULL || r < V.np;
-            x[k] = live ? ld_stream(base + (int64_t)r * 4) : make_uint4(0, 0, 0, 0);
+            const bool live = (LM & kFull) || r < V.np;
+            x[k] = live ? ld16<(LM & kStream) != 0>(base + (int64_t)r * 4) : make_uint4(0, 0, 0, 0);
             e[k] = live ? ex[r >> 5] : 0u;
         }
     }
@@ -243,12 +260,12 @@ struct Tile<CB_FRSZ2_16> {
     using M = Map<CB_FRSZ2_16>;
     uint4 x;
     uint32_t e;
-    template <bool FULL>
+    template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         const unsigned char* base = V.values + (int64_t)col * V.col_bytes;
         const int r = tile0 + M::group_row(lane, 0);
-        const bool live = FULL || r < V.np;
-        x = live ? ld_stream(base + (int64_t)r * 2) : make_uint4(0, 0, 0, 0);
+        const bool live = (LM & kFull) || r < V.np;
+        x = live ? ld16<(LM & kStream) != 0>(base + (int64_t)r * 2) : make_uint4(0, 0, 0, 0);
         e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
     }
     __device__ __forceinline__ double m(int q) const {
@@ -284,14 +301,14 @@ struct Tile<CB_FRSZ2_21> {
     uint32_t y[6];
     uint32_t e;
     uint32_t s;
-    template <bool FULL>
+    template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         const uint32_t* base = reinterpret_cast<const uint32_t*>(V.values + (int64_t)col * V.col_bytes);
         const int r = tile0 + 8 * lane;
-        const bool live = FULL || r < V.np;
+        const bool live = (LM & kFull) || r < V.np;
         const uint32_t* p = base + (int64_t)(r >> 5) * 21 + 5 * (lane & 3);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = live ? __builtin_nontemporal_load(p + k) : 0u;
+        for (int k = 0; k < 6; ++k) y[k] = live ? ld4<(LM & kStream) != 0>(p + k) : 0u;
         e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
         s = 8u * (lane & 3);
     }
@@ -334,12 +351,12 @@ struct Tile<CB_FRSZ2_21> {
     }
 };
 
-// Load U columns of a tile.
-template <int FMT, int U, bool FULL>
+// Load U columns of a tile (load mode M).
+template <int FMT, int U, int LM>
 __device__ __forceinline__ void load_tiles(Tile<FMT>* t, const BasisView& V, const int* cols, int tile0,
                                            int lane) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) t[u].template load<FULL>(V, cols[u], tile0, lane);
+    for (int u = 0; u < U; ++u) t[u].template load<LM>(V, cols[u], tile0, lane);
 }
 
 // ----------------------------------------------------------------- writing tiles

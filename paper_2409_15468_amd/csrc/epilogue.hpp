@@ -5,10 +5,11 @@
 // counter; the workgroup that draws the last ticket sums the partials in
 // workgroup-index order (so the result does not depend on which workgroup
 // finished last), stores or applies the sums, and resets the counter for the
-// next launch on the stream.  Partials are written and read with device-scope
-// (agent) relaxed atomic accesses, which are coherent across the XCDs' L2
-// caches, and each thread waits for its stores to complete before the ticket
-// is drawn; no cache-wide writeback or invalidate is needed.
+// next launch on the stream.  Partials are written with device-scope (agent)
+// relaxed atomic stores, which are coherent across the XCDs' L2 caches, and
+// each thread waits for its stores to complete before the ticket is drawn; the
+// last workgroup alone then acquires at device scope (one cache invalidate
+// per launch) and reads the partials with ordinary loads.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,7 +55,9 @@ struct Epi {
     int ncols;             // sums to form
     int G;                 // partials per column (column stride of `partials`)
     double* out;           // EPI_STORE / EPI_REORTH_PROJECT (u)
-    unsigned* counter;
+    unsigned* counter;     // ticket counters (counter_words(G) words, zero between launches)
+    const double* extra;   // EPI_STEP_CHECK: the SpMV's ||A v||^2 partials
+    int extra_G;
     // solver context (modes 1-3)
     State* st;
     double* H;             // column-major (m+1) x m
@@ -72,24 +75,29 @@ namespace dev {
 __device__ __forceinline__ void store_partial(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double load_partial(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum partials[c * G + g] over g for c < ncols into sums[c] (LDS, ncols <= 256)
-// or out; two threads per column, each over half of the workgroups in order.
+// Sums of partials[c * G + g] over g for the nc columns c0 .. c0+nc-1 (nc <=
+// 256), into lds[c - c0].  tpc = 256 / nc threads share a column: thread s of
+// the column sums g = s, s + tpc, ... in order, then the tpc sums are added in
+// index order.
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int G, int c0, int nc,
-                                                double* lds2) {
-    const int half = (G + 1) / 2;
-    for (int idx = threadIdx.x; idx < 2 * nc; idx += blockDim.x) {
-        const int c = c0 + (idx >> 1);
-        const int lo = (idx & 1) ? half : 0;
-        const int hi = (idx & 1) ? G : half;
-        const double* p = partials + (int64_t)c * G;
-        double s = 0.0;
-        for (int k = lo; k < hi; ++k) s += load_partial(p + k);
-        lds2[idx] = s;
+                                                double* lds) {
+    const int tpc = 256 / nc;
+    const int t = threadIdx.x;
+    double s = 0.0;
+    if (t < tpc * nc) {
+        const double* p = partials + (int64_t)(c0 + t / tpc) * G;
+        for (int k = t % tpc; k < G; k += tpc) s += p[k];
     }
+    lds[t] = s;
+    __syncthreads();
+    if (t < nc) {
+        double u = lds[t * tpc];
+        for (int k = 1; k < tpc; ++k) u += lds[t * tpc + k];
+        lds[256 + t] = u;
+    }
+    __syncthreads();
+    if (t < nc) lds[t] = lds[256 + t];
+    __syncthreads();
 }
 
 // Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
@@ -149,74 +157,108 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
 // rotations for the Givens update of the solver modes.
 constexpr int kEpiLds = 3 * (kMaxRestart + 2) > 512 ? 3 * (kMaxRestart + 2) : 512;
 
-// Run by every workgroup of the launch after its partials are written
-// (all threads; blockDim.x == 256).
-__device__ __forceinline__ void epilogue(const Epi& e, const double* __restrict__ partials, double* lds) {
+// Ticket counters: a top counter and one counter per group of 32 workgroups,
+// each in its own 128-byte line (same-address device-scope atomics serialise,
+// so a single counter for ~1000 workgroups costs tens of microseconds).
+constexpr int kTicketGroup = 32;
+constexpr int kCounterLine = 32;  // unsigned words per 128-byte line
+__host__ __device__ constexpr int counter_words(int groups) {
+    return kCounterLine * (1 + (groups + kTicketGroup - 1) / kTicketGroup);
+}
+
+// True in the workgroup that finishes last.  Each workgroup's partial stores
+// complete before its ticket is drawn; the last workgroup of each group of 32
+// then draws a ticket from the top counter.  Counters are reset for the next
+// launch by the workgroups that drew their last tickets.
+__device__ __forceinline__ bool last_workgroup(unsigned* counters) {
     __shared__ int is_last;
     __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned total = gridDim.x * gridDim.y;
-        is_last = __hip_atomic_fetch_add(e.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                  total - 1;
+        const unsigned g = blockIdx.x + gridDim.x * blockIdx.y, G = gridDim.x * gridDim.y;
+        const unsigned grp = g / kTicketGroup;
+        const unsigned gsize = min((unsigned)kTicketGroup, G - grp * kTicketGroup);
+        const unsigned ngrp = (G + kTicketGroup - 1) / kTicketGroup;
+        unsigned* gc = counters + kCounterLine * (1 + grp);
+        int last = 0;
+        if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+            *gc = 0u;
+            if (__hip_atomic_fetch_add(counters, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1) {
+                *counters = 0u;
+                last = 1;
+            }
+        }
+        is_last = last;
     }
     __syncthreads();
-    if (!is_last) return;
+    if (!is_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+// sum of partials[0 .. G) in a fixed order, valid in thread 0
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int G) {
+    double t = 0.0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) t += p[k];
+    return block_sum<256>(t);
+}
+
+// Run by every workgroup of the launch after its partials are written
+// (all threads; blockDim.x == 256; at most 2016 workgroups).
+__device__ __forceinline__ void epilogue(const Epi& e, const double* __restrict__ partials, double* lds) {
+    if (!last_workgroup(e.counter)) return;
     if ((e.mode == EPI_STORE && e.ncols > 1) || e.mode == EPI_REORTH_PROJECT) {
         for (int c0 = 0; c0 < e.ncols; c0 += 256) {
             const int nc = min(256, e.ncols - c0);
             reduce_partials(partials, e.G, c0, nc, lds);
-            __syncthreads();
             for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-                const double u = lds[2 * i] + lds[2 * i + 1];
+                const double u = lds[i];
                 e.out[c0 + i] = u;
                 if (e.mode == EPI_REORTH_PROJECT) e.H[(int64_t)e.j * (e.m + 1) + c0 + i] += u;
             }
             __syncthreads();
         }
-    } else {
-        // one sum (a squared norm): every thread sums its share, then a block sum
-        double t = 0.0;
-        for (int k = threadIdx.x; k < e.G; k += blockDim.x) t += load_partial(partials + k);
-        t = block_sum<256>(t);
-        if (e.mode == EPI_STORE) {
-            if (threadIdx.x == 0) {
-                e.out[0] = t;
-                *e.counter = 0u;
-            }
-            return;
-        }
-        __shared__ int do_finish, bd;
-        __shared__ double hn_s;
-        if (threadIdx.x == 0) {
-            State& s = *e.st;
-            do_finish = 0;
-            bd = 0;
-            s.hn2 = t;
-            s.hn = sqrt(t);
-            hn_s = s.hn;
-            if (e.mode == EPI_STEP_CHECK) {
-                s.omega = sqrt(s.om2);
-                s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
-                if (s.hn < s.eta * s.omega) {
-                    s.reorth = 1;  // steps 7-11 follow
-                    s.omega_pre = s.hn;
-                } else {
-                    s.reorth = 0;
-                    do_finish = 1;
-                }
-            } else {  // EPI_REORTH_FINISH
-                s.reorths += 1;
-                s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
-                bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
+        return;
+    }
+    // one sum (a squared norm)
+    const double t = sum_partials(partials, e.G);
+    if (e.mode == EPI_STORE) {
+        if (threadIdx.x == 0) e.out[0] = t;
+        return;
+    }
+    // the SpMV's ||A v||^2 partials, when this step needs omega
+    double om2 = 0.0;
+    if (e.mode == EPI_STEP_CHECK) om2 = sum_partials(e.extra, e.extra_G);
+    __shared__ int do_finish, bd;
+    __shared__ double hn_s;
+    if (threadIdx.x == 0) {
+        State& s = *e.st;
+        do_finish = 0;
+        bd = 0;
+        s.hn2 = t;
+        s.hn = sqrt(t);
+        hn_s = s.hn;
+        if (e.mode == EPI_STEP_CHECK) {
+            s.om2 = om2;
+            s.omega = sqrt(om2);
+            s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
+            if (s.hn < s.eta * s.omega) {
+                s.reorth = 1;  // steps 7-11 follow
+                s.omega_pre = s.hn;
+            } else {
                 s.reorth = 0;
                 do_finish = 1;
             }
+        } else {  // EPI_REORTH_FINISH
+            s.reorths += 1;
+            s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
+            bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
+            s.reorth = 0;
+            do_finish = 1;
         }
-        __syncthreads();
-        if (do_finish) finish_step(e, bd, hn_s, lds);
     }
-    if (threadIdx.x == 0) *e.counter = 0u;
+    __syncthreads();
+    if (do_finish) finish_step(e, bd, hn_s, lds);
 }
 
 }  // namespace dev

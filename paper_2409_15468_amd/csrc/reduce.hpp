@@ -88,6 +88,7 @@ __device__ __forceinline__ double block_sum(double v) {
 #pragma unroll
         for (int k = 1; k < NT / 64; ++k) t += part[k];
     }
+    __syncthreads();  // part[] may be reused by the next call
     return t;
 }
 

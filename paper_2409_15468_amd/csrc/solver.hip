@@ -8,7 +8,8 @@
 // to a control block in device memory.  A step is six launches: SpMV (+ its
 // norm), projection (+ h), update (+ norm and step 7 test), the second
 // projection and update when step 7 asks for them (+ breakdown test and Givens
-// rotation), and the normalise-and-store of the next basis vector.  The host
+// rotation), and the normalise-and-store of the next basis vector; the SpMV's
+// norm is summed by the first update's last workgroup.  The host
 // enqueues a whole cycle of m steps without waiting; kernels of steps after
 // the cycle has ended read the control block and return at once.  The host
 // waits once per cycle, after the explicit residual of the restart (step 1 /
@@ -27,7 +28,7 @@ namespace cb {
 using namespace dev;
 
 struct Layout {
-    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, total;
+    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, part_s, total;
 };
 
 static int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -38,7 +39,7 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     auto take = [&](int64_t bytes) { int64_t o = off; off += al(bytes); return o; };
     L.state = take(sizeof(State));
     L.flag = take(sizeof(int32_t));
-    L.counter = take(sizeof(unsigned));
+    L.counter = take(kCounterBytes);
     L.H = take((int64_t)(m + 1) * m * 8);
     L.cs = take((int64_t)m * 8);
     L.sn = take((int64_t)m * 8);
@@ -52,9 +53,8 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     L.exps = take(exponent_words(fmt, n) * 4 * (m + 1));
     // partial sums: the basis kernels' groups times columns, or one per SpMV
     // workgroup (at least 4 rows each)
-    int64_t pb = (int64_t)row_groups(n) * (m + 1);
-    int64_t ps = (int64_t)n / 4 + 1;
-    L.part = take(8 * (pb > ps ? pb : ps));
+    L.part = take(8 * (int64_t)project_groups(n) * (m + 1));
+    L.part_s = take(8 * ((int64_t)n / 4 + 1));  // SpMV partials: at least 4 rows per workgroup
     L.total = off;
     return L;
 }
@@ -72,6 +72,7 @@ __global__ void k_sumsq(const double* __restrict__ x, int n, double* __restrict_
 
 __global__ void k_init(State* st, int32_t* flag, unsigned* counter, double tol, double eta, int max_iters,
                        int literal) {
+    for (int i = threadIdx.x; i < kCounterBytes / 4; i += blockDim.x) counter[i] = 0u;
     if (threadIdx.x != 0) return;
     State z = {};
     z.nb = sqrt(st->r2);
@@ -92,19 +93,24 @@ __global__ void k_init(State* st, int32_t* flag, unsigned* counter, double tol, 
     }
     *st = z;
     *flag = 0;
-    *counter = 0u;
 }
 
-// Step 1 / 18: beta = ||b - A x|| and the stop test of Eq. 4.
-__global__ void k_cycle_begin(State* st, const int32_t* flag, double* g, int m) {
+// Step 1 / 18: beta = ||b - A x|| from the residual SpMV's partials and the
+// stop test of Eq. 4.
+__global__ __launch_bounds__(256) void k_cycle_begin(State* st, const int32_t* flag, double* g, int m,
+                                                     const double* __restrict__ partials, int G) {
     const int t = threadIdx.x;
     __shared__ int go;
+    double r2 = 0.0;
+    for (int k = t; k < G; k += blockDim.x) r2 += partials[k];
+    r2 = block_sum<256>(r2);
     if (t == 0) {
         State& s = *st;
         s.prev_steps = s.steps;
         s.steps = 0;
         s.active = 0;
         s.reorth = 0;
+        s.r2 = r2;
         s.beta = sqrt(s.r2);
         s.rel = s.beta / s.nb;
         go = 0;
@@ -215,6 +221,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     double* w = W.at<double>(W.L.w);
     double* v = W.at<double>(W.L.v);
     double* part = W.at<double>(W.L.part);
+    double* part_s = W.at<double>(W.L.part_s);
+    const int Gs = spmv_groups(n, A.nnz);
     cb_basis V{fmt, n, m + 1, 0, W.base + W.L.vals,
                frsz2_bits_of(fmt) ? W.at<uint32_t>(W.L.exps) : nullptr};
     const double cbytes = (double)column_bytes(fmt, n);
@@ -245,7 +253,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
 
     // ||b||, tolerances, counters
     enqueue_sumsq(b, n, part, &st->r2, s);
-    k_init<<<1, 64, 0, s>>>(st, flag, counter, tol, eta, max_iters, literal);
+    k_init<<<1, 256, 0, s>>>(st, flag, counter, tol, eta, max_iters, literal);
     CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
     CB_HIP(hipStreamSynchronize(s));
     if (hs->stop) {
@@ -255,10 +263,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
         bool capped = false;
         for (;;) {
             // restart: explicit residual into w, beta, stop test
-            Epi e = sum_e;
-            e.out = &st->r2;
-            launch_spmv(A, x, b, w, part, 1, nullptr, e, s);
-            k_cycle_begin<<<1, 64, 0, s>>>(st, flag, g, m);
+            launch_spmv(A, x, b, w, part_s, 1, nullptr, s);
+            k_cycle_begin<<<1, 256, 0, s>>>(st, flag, g, m, part_s, Gs);
             CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
             if (cycles > 0) CB_HIP(hipMemcpyAsync(hh, hist, (size_t)m * 8, hipMemcpyDeviceToHost, s));
             CB_HIP(hipStreamSynchronize(s));
@@ -271,15 +277,16 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
             launch_store(fmt, V, 0, w, &st->beta, v, flag, active, s);
             for (int j = 0; j < m; ++j) {
                 double* hcol = H + (int64_t)j * (m + 1);
-                Epi eo = sum_e;          // omega^2 = ||A v||^2
-                eo.out = &st->om2;
-                launch_spmv(A, v, nullptr, w, part, 0, active, eo, s);
+                // w = A v; its ||w||^2 partials go to the first update's epilogue
+                launch_spmv(A, v, nullptr, w, part_s, 0, active, s);
                 Epi eh = sum_e;          // h_{1:j+1,j}
                 eh.out = hcol;
                 launch_project(fmt, V, j + 1, w, part, active, eh, s);
-                Epi ec = step_e;         // ||w||, step 7 test, maybe Givens
+                Epi ec = step_e;         // omega, ||w||, step 7 test, maybe Givens
                 ec.mode = EPI_STEP_CHECK;
                 ec.j = j;
+                ec.extra = part_s;
+                ec.extra_G = Gs;
                 launch_subtract(fmt, V, j + 1, nullptr, hcol, w, part, active, -1, ec, s);
                 Epi eu = step_e;         // u = V^T w, h += u
                 eu.mode = EPI_REORTH_PROJECT;
@@ -419,12 +426,8 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
         goto done;
     }
     for (;;) {
-        Epi e{};
-        e.mode = EPI_STORE;
-        e.out = scal;
-        e.counter = W.at<unsigned>(W.L.counter);
-        launch_zero_counter(e.counter, s);
-        launch_spmv(*A, x, b, r, part, 1, nullptr, e, s);
+        launch_spmv(*A, x, b, r, part, 1, nullptr, s);
+        launch_reduce(part, spmv_groups(n, A->nnz), 1, scal, 0, nullptr, s);
         if (hipMemcpyAsync(hv, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { status = fail(CB_ERR_HIP, "copy failed"); goto done; }
         const double rn = std::sqrt(hv[0]);

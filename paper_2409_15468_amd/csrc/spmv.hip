@@ -23,9 +23,8 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
                                               const double* __restrict__ x,
                                               const double* __restrict__ b, double* __restrict__ y,
                                               double* __restrict__ partials, int mode,
-                                              const int* __restrict__ guard, Epi e) {
+                                              const int* __restrict__ guard) {
     if (guard && *guard == 0) return;
-    __shared__ double elds[kEpiLds];
     constexpr int RPW = 256 / LPR;
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
@@ -44,8 +43,7 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     }
     if (partials) {
         double t = block_sum<256>(out * out);
-        if (threadIdx.x == 0) store_partial(partials + blockIdx.x, t);
-        epilogue(e, partials, elds);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
 
@@ -62,15 +60,12 @@ int spmv_groups(int32_t n, int32_t nnz) {
 }
 
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
-                 int mode, const int* guard, const Epi& e, hipStream_t s) {
+                 int mode, const int* guard, hipStream_t s) {
     const int lpr = spmv_lanes_per_row(A.n, A.nnz);
     const int G = spmv_groups(A.n, A.nnz);
-    Epi ee = e;
-    ee.G = G;
-    ee.ncols = 1;
 #define CB_SPMV_CASE(L)                                                                         \
     case L:                                                                                     \
-        k_spmv<L><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard, ee); \
+        k_spmv<L><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard); \
         break;
     switch (lpr) {
         CB_SPMV_CASE(1)

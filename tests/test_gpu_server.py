@@ -1,0 +1,87 @@
+"""Serving (cb_server_*): HBM-budget admission, continuous batching and result
+independence from the mix.
+
+* Each request's solution is bit-identical whether it ran alone on the
+  server or among others (same kernels, same reduction order per request),
+  and meets its own tolerance.
+* A budget that fits one request at a time forces queueing; every request
+  still completes, in FIFO admission order.
+* A request larger than the whole budget is rejected with CB_ERR_OVER_BUDGET.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2409_15468_amd as cb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def requests(k):
+    reqs = synth.serving_requests(count=k, seed=4, n_max=40 ** 3)
+    return [(r, r.system()) for r in reqs]
+
+
+def run_all(server, items, stagger=0.0):
+    tickets = []
+    for r, s in items:
+        tickets.append(server.submit(s.A.row_ptr, s.A.col, s.A.val, s.b, r.m, r.tol, r.fmt))
+        if stagger:
+            time.sleep(stagger)
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 120:
+        for (r, s), t in zip(items, tickets):
+            if r.rid in out:
+                continue
+            got = server.poll(t, s.A.n)
+            if got is not None:
+                out[r.rid] = got
+        time.sleep(0.002)
+    assert len(out) == len(tickets), "server did not finish in time"
+    return out
+
+
+def test_alone_equals_mixed_and_meets_tolerance():
+    items = requests(24)
+    srv = cb.Server(8 << 30, 0, lanes=6)
+    mixed = run_all(srv, items, stagger=0.001)
+    charged, queued, running = srv.stats()
+    assert charged == 0 and queued == 0 and running == 0
+    srv.close()
+    for r, s in items:
+        x, res, times = mixed[r.rid]
+        assert res["status"] == 0 and res["converged"], (r, res)
+        rel = np.linalg.norm(s.b - s.A.scipy() @ x) / np.linalg.norm(s.b)
+        assert rel <= r.tol * (1 + 1e-6)
+        assert times[0] <= times[1] <= times[2]
+    # the same requests one at a time
+    alone_srv = cb.Server(8 << 30, 0, lanes=1)
+    for r, s in items[:8]:
+        got = run_all(alone_srv, [(r, s)])[r.rid]
+        assert np.array_equal(got[0].view(np.uint64), mixed[r.rid][0].view(np.uint64)), r
+        assert got[1]["iterations"] == mixed[r.rid][1]["iterations"]
+    alone_srv.close()
+
+
+def test_budget_forces_queueing_and_rejects_oversize():
+    items = requests(6)
+    need = max(cb.Server.request_bytes(s.A.n, s.A.nnz, r.m, r.fmt) for r, s in items)
+    srv = cb.Server(need, 0, lanes=4)
+    out = run_all(srv, items)
+    spans = [(out[r.rid][2][1], out[r.rid][2][2], cb.Server.request_bytes(s.A.n, s.A.nnz, r.m, r.fmt))
+             for r, s in items]
+    for t0, _, _ in spans:  # at every admission the running set fits the budget
+        assert sum(b for s0, e0, b in spans if s0 <= t0 < e0) <= need
+    # FIFO admission: requests start in submission order
+    starts = [out[r.rid][2][1] for r, _ in items]
+    assert starts == sorted(starts)
+    big = synth.sweep_3d(N=60, seed=1)
+    assert cb.Server.request_bytes(big.A.n, big.A.nnz, 100, "float64") > need
+    with pytest.raises(cb.CbError) as ei:
+        srv.submit(big.A.row_ptr, big.A.col, big.A.val, big.b, 100, 1e-8, "float64")
+    assert ei.value.status == cb.CB_ERR_OVER_BUDGET
+    srv.close()
