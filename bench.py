@@ -128,6 +128,111 @@ def cpu_baseline(s, gpu_iters, gpu_cycles, m, sample_steps=40):
     }
 
 
+def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
+    """Continuous-batching server on the seeded request stream: requests are
+    submitted at their Poisson arrival times, results polled as they finish.
+    Latency = finish - submit on the server's clock."""
+    import synth
+    reqs = synth.serving_requests(count, rate, seed)
+    log(f"serving: building {count} systems")
+    t = time.time()
+    mats = {}
+    systems = []
+    for r in reqs:
+        key = (r.dim, r.N)
+        if key not in mats:
+            mats[key] = synth.convection_diffusion(r.N, r.dim, (20.0, 0.0) if r.dim == 2 else (10.0, 5.0, 2.0))
+        A = mats[key]
+        xs = np.random.default_rng(r.seed).uniform(-1.0, 1.0, A.n)
+        systems.append((A, synth.rhs_from_solution(A, xs)))
+    log(f"serving: inputs ready in {time.time() - t:.1f}s ({len(mats)} distinct matrices)")
+    server = cb.Server(int(budget_gb * (1 << 30)), 0, lanes)
+    pending = {}
+    done = {}
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < count or pending:
+        now = time.perf_counter() - t0
+        while nxt < count and reqs[nxt].arrival_s <= now:
+            A, b = systems[nxt]
+            tk = server.submit(A.row_ptr, A.col, A.val, b, reqs[nxt].m, reqs[nxt].tol, reqs[nxt].fmt)
+            pending[tk] = nxt
+            nxt += 1
+        for tk in list(pending):
+            out = server.poll(tk, systems[pending[tk]][0].n)
+            if out is not None:
+                done[pending.pop(tk)] = out
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    server.close()
+    lat = np.array([done[i][2][2] - done[i][2][0] for i in range(count)])
+    queue = np.array([done[i][2][1] - done[i][2][0] for i in range(count)])
+    first = min(done[i][2][0] for i in range(count))
+    last = max(done[i][2][2] for i in range(count))
+    ok = 0
+    worst = 0.0
+    for i in range(count):
+        A, b = systems[i]
+        x, res, _ = done[i]
+        rrn = float(np.linalg.norm(b - A.scipy() @ x) / np.linalg.norm(b))
+        worst = max(worst, rrn / reqs[i].tol)
+        ok += int(res["status"] == 0 and res["converged"] and rrn <= reqs[i].tol * (1 + 1e-6))
+    small = np.array([reqs[i].n <= 16384 for i in range(count)])
+    out = {"requests": count, "rate_per_s": rate, "budget_gb": budget_gb, "lanes": lanes,
+           "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+           "mean_latency_s": float(lat.mean()), "p50_queue_s": float(np.percentile(queue, 50)),
+           "solves_per_s": count / (last - first), "makespan_s": last - first, "wall_s": wall,
+           "small_requests": int(small.sum()),
+           "p50_latency_small_s": float(np.percentile(lat[small], 50)) if small.any() else None,
+           "p50_latency_large_s": float(np.percentile(lat[~small], 50)) if (~small).any() else None,
+           "converged_within_tol": ok, "worst_rrn_over_tol": worst}
+    log(f"serving: p50 {out['p50_latency_s'] * 1e3:.1f} ms, p99 {out['p99_latency_s'] * 1e3:.1f} ms, "
+        f"{out['solves_per_s']:.1f} solves/s, {ok}/{count} within tol")
+    return out
+
+
+def precision_bench(cb, torch, steps, warmup):
+    """FP64 iterative refinement around GMRES(100) on a frsz2_16 basis (inner
+    tolerance 1e-4 relative, one cycle per outer step) against plain
+    GMRES(100) on a float64 basis, both to 1e-12, on the banded random system
+    (n = 2^22, 27 nonzeros per row, |i - j| <= 1000, seed 3)."""
+    import synth
+    log("precision: building the banded system")
+    t = time.time()
+    s = synth.banded_random(seed=3)
+    log(f"precision: inputs ready in {time.time() - t:.1f}s (n={s.A.n}, nnz={s.A.nnz})")
+    A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    b = torch.from_numpy(s.b).cuda()
+    x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    out = {}
+
+    def run(fn):
+        for _ in range(warmup):
+            x.zero_()
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    t_ir, r_ir = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, 1e-4, 1e-12, "frsz2_16"))
+    x_ir = x.cpu().numpy()
+    t_64, r_64 = run(lambda: cb.cbgmres_solve(A, b, x, 100, 1e-12, "float64")[0])
+    x_64 = x.cpu().numpy()
+    for name, tt, r, xx in (("ir_frsz2_16", t_ir, r_ir, x_ir), ("float64", t_64, r_64, x_64)):
+        rrn = float(np.linalg.norm(s.b - s.A.scipy() @ xx) / np.linalg.norm(s.b))
+        out[name] = {"seconds": tt, "iterations": r["iterations"], "outer_or_cycles": r["restarts"],
+                     "converged": bool(r["converged"]), "rel_residual": rrn,
+                     "err_vs_xstar": float(np.linalg.norm(xx - s.x_star) / np.linalg.norm(s.x_star))}
+        log(f"precision {name}: {tt * 1e3:.1f} ms, {r['iterations']} iterations, rrn {rrn:.2e}")
+    out["err_ir_vs_float64_solve"] = float(np.linalg.norm(x_ir - x_64) / np.linalg.norm(x_64))
+    out["speedup_ir_vs_float64"] = t_64 / t_ir
+    return out, s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +247,14 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="microbench only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy 1 GiB once: the reference kernel for FETCH/WRITE_SIZE")
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "serving", "precision"],
+                    help="sweep: the n=1e6 solve + kernel microbench (default); serving: the "
+                         "request stream through the continuous-batching server; precision: FP64 "
+                         "iterative refinement around a frsz2_16-basis GMRES at n=2^22")
+    ap.add_argument("--serve-count", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-lanes", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -153,6 +266,30 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload == "serving":
+        sv = serving_bench(cb, torch, args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_lanes)
+        rec = {"metric": "serving p50/p99 latency and solves/s", "value": sv["solves_per_s"],
+               "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sv["wall_s"] * 1e3,
+               "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"{args.serve_count} seeded convection-diffusion solve requests, Poisson "
+                                      f"arrivals {args.serve_rate}/s, n 32^2..128^3, formats f32/frsz2_16/21/32, "
+                                      f"tol 1e-12..1e-8, m 30..100, HBM budget {args.serve_budget_gb} GB"},
+               "serving": sv}
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "precision":
+        pv, ps = precision_bench(cb, torch, args.steps, args.warmup)
+        rec = {"metric": "time-to-1e-12 residual, FP64 IR around frsz2_16-basis GMRES(100) vs fp64-basis "
+                         "GMRES(100)", "value": pv["ir_frsz2_16"]["seconds"], "unit": "s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": pv["ir_frsz2_16"]["seconds"] * 1e3,
+               "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"banded random n={ps.A.n}, nnz={ps.A.nnz} (27 per row, |i-j|<=1000, "
+                                      "diagonal 1.2 x row sum, seed 3), tol 1e-12"},
+               "precision": pv}
+        print(json.dumps(rec), flush=True)
+        return
     m, tol = 100, 1e-10
     log(f"bench: building cd3d N={args.grid}")
     s = synth.sweep_3d(N=args.grid, seed=1)

@@ -235,13 +235,62 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
                      void* stream);
 
 /* ======================================================================
+ * Batched solves of small systems (the serving path's packing of small
+ * requests into one persistent launch).  Each system is solved by the method
+ * of cbgmres_solve (Fig. 1 with restarts, Eq. 4 stop test, same options and
+ * statistics) inside ONE workgroup that keeps all of its state -- basis,
+ * vectors, H, Givens rotations -- on the GPU for the whole solve; the
+ * workgroups of a launch take systems from the list until it is empty.  A
+ * system's result does not depend on the rest of the batch (fixed reduction
+ * order inside the workgroup); it may differ in the last bits from
+ * cbgmres_solve on the same system, whose reductions are ordered across
+ * workgroups.
+ * ====================================================================== */
+typedef struct cb_batch_item {
+    cb_csr A;                /* device CSR, 1 <= n <= cbgmres_batch_max_n() */
+    const double* b;         /* device float64[n] */
+    double* x;               /* device float64[n]: x0 on entry, the iterate on return */
+    void* workspace;         /* device, 256-byte aligned, owned by the caller, at least
+                                cbgmres_batch_workspace_bytes(n, m, format) bytes; on
+                                return it holds the last cycle's basis, column c at
+                                byte c * cb_basis_column_bytes(format, n), followed (frsz2)
+                                by the exponent words, column c at word
+                                c * cb_basis_exponent_words(format, n) of a 256-byte
+                                aligned array */
+    size_t workspace_bytes;
+    int32_t m;               /* restart length, 1 <= m <= cbgmres_batch_max_restart() */
+    int32_t format;          /* cb_basis_format */
+    double tol;              /* relative residual, > 0 */
+} cb_batch_item;
+
+/* Largest n and m a batch item may have. */
+int32_t cbgmres_batch_max_n(void);
+int32_t cbgmres_batch_max_restart(void);
+
+/* Device workspace bytes of one batch item; -1 if the shape is out of range. */
+int64_t cbgmres_batch_workspace_bytes(int32_t n, int32_t m, int format);
+
+/* Solve `count` systems in one launch on `stream`.  items (host array) and the
+ * options (nullable, as for cbgmres_solve) are read before return;
+ * results_host[i] receives system i's statistics (seconds = the batch's wall
+ * time).  Synchronous.  Returns CB_ERR_INVALID_ARG / CB_ERR_WORKSPACE (nothing
+ * launched) for a bad item, else CB_OK if every system converged, else the
+ * status of the first that did not. */
+int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_options* opt,
+                        cb_result* results_host, void* stream);
+
+/* ======================================================================
  * Serving: continuous batching of solve requests on one GPU.
  * Requests are admitted while their device footprint fits in the HBM budget
  * (basis n*(m+1) stored bytes + CSR + work vectors); later arrivals wait in
  * FIFO order and are admitted as earlier solves finish and release memory.
- * Admitted solves run concurrently on a pool of HIP streams.  Each solve runs
- * the same kernels with the same reduction order as cbgmres_solve, so its
- * result does not depend on what else runs beside it.
+ * Admitted solves run concurrently on a pool of lanes (host threads, each
+ * with its own HIP stream).  Small requests (n <= 16384, m <=
+ * cbgmres_batch_max_restart()) at the head of the queue are taken together and
+ * solved in one persistent launch of the batched solver (cbgmres_solve_batch);
+ * larger ones run cbgmres_solve on a lane of their own.  The path depends on a
+ * request's shape only and neither path's arithmetic depends on the other
+ * requests, so a result is the same alone and in any mix.
  * ====================================================================== */
 typedef struct cb_server cb_server;
 

@@ -56,6 +56,12 @@ class cb_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cb_batch_item(C.Structure):
+    _fields_ = [("A", cb_csr), ("b", C.c_void_p), ("x", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("m", C.c_int32), ("format", C.c_int32),
+                ("tol", C.c_double)]
+
+
 # name -> (restype, argtypes); the full C ABI of include/cbgmres.h
 _P, _I32, _I64, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
 SIGNATURES = {
@@ -80,6 +86,11 @@ SIGNATURES = {
                                 _P, _SZ, _P, _I64, C.POINTER(cb_result), _P]),
     "cbgmres_ir_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _D, C.c_int, _I32,
                                    C.POINTER(cb_result), _P]),
+    "cbgmres_batch_max_n": (_I32, []),
+    "cbgmres_batch_max_restart": (_I32, []),
+    "cbgmres_batch_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
+    "cbgmres_solve_batch": (C.c_int, [C.POINTER(cb_batch_item), _I32, C.POINTER(cb_options),
+                                      C.POINTER(cb_result), _P]),
     "cb_server_create": (_P, [_SZ, C.c_int, C.c_int]),
     "cb_server_request_bytes": (_I64, [_I32, _I32, _I32, C.c_int]),
     "cb_server_submit": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _I32, _D, C.c_int,
@@ -406,6 +417,60 @@ def cbgmres_ir_solve(A: DeviceCSR, b, x, m: int, inner_tol: float, tol: float, f
         _check(st, "cbgmres_ir_solve")
     out = res.as_dict()
     out["status"] = st
+    return out
+
+
+def cbgmres_batch_max_n() -> int:
+    return int(lib().cbgmres_batch_max_n())
+
+
+def cbgmres_batch_max_restart() -> int:
+    return int(lib().cbgmres_batch_max_restart())
+
+
+def cbgmres_batch_workspace_bytes(n: int, m: int, fmt) -> int:
+    return int(lib().cbgmres_batch_workspace_bytes(n, m, _fmt(fmt)))
+
+
+def cbgmres_solve_batch(systems, eta: float = 0.0, max_iters: int = 0, literal_breakdown: bool = False,
+                        workspaces=None, stream=None, check: bool = True):
+    """Solve several small systems in one launch, one workgroup each.
+    systems: list of (A: DeviceCSR, b, x, m, tol, fmt); x is updated in place.
+    workspaces: optional list of uint8 device tensors (one per system, at least
+    cbgmres_batch_workspace_bytes); allocated here when None.  Returns the
+    list of result dicts (status per system)."""
+    import torch
+    count = len(systems)
+    items = (cb_batch_item * max(count, 1))()
+    keep = []
+    for i, (A, b, x, m, tol, fmt) in enumerate(systems):
+        _dev(x, torch.float64, "x")
+        _dev(b, torch.float64, "b")
+        if x.numel() != A.n or b.numel() != A.n:
+            raise ValueError("x and b must have n entries")
+        nbytes = cbgmres_batch_workspace_bytes(A.n, m, fmt)
+        if workspaces is None:
+            ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=x.device)
+        else:
+            ws = workspaces[i]
+        keep.append(ws)
+        items[i].A = A.desc()
+        items[i].b = b.data_ptr()
+        items[i].x = x.data_ptr()
+        items[i].workspace = ws.data_ptr()
+        items[i].workspace_bytes = ws.numel()
+        items[i].m = m
+        items[i].format = _fmt(fmt)
+        items[i].tol = tol
+    opt = cb_options(eta, max_iters, 0, int(literal_breakdown), 0)
+    res = (cb_result * max(count, 1))()
+    st = lib().cbgmres_solve_batch(items, count, C.byref(opt), res, _stream(stream))
+    if check and st not in (CB_OK, CB_ERR_NOT_CONVERGED, CB_ERR_NONFINITE):
+        _check(st, "cbgmres_solve_batch")
+    out = []
+    for i in range(count):
+        d = res[i].as_dict()
+        out.append(d)
     return out
 
 

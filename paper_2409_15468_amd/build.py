@@ -9,8 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbgmres.so")
-SOURCES = ["api.hip", "basis.hip", "spmv.hip", "solver.hip", "server.cpp"]
-HEADERS = ["cb_internal.hpp", "codec.hpp", "reduce.hpp", "epilogue.hpp"]
+SOURCES = ["api.hip", "basis.hip", "spmv.hip", "solver.hip", "batch.hip", "server.cpp"]
+HEADERS = ["cb_internal.hpp", "codec.hpp", "reduce.hpp", "epilogue.hpp", "tiles.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

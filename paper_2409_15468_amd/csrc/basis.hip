@@ -11,6 +11,7 @@
 #include "codec.hpp"
 #include "epilogue.hpp"
 #include "reduce.hpp"
+#include "tiles.hpp"
 
 namespace cb {
 
@@ -25,7 +26,6 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
                                                     double* v_out, int32_t* __restrict__ flag,
                                                     const int* __restrict__ guard) {
     if (guard && *guard == 0) return;
-    using M = Map<FMT>;
     const int lane = threadIdx.x & 63;
     const int tile0 = blockIdx.x * kRowsPerWG + (threadIdx.x >> 6) * kTile;
     double v[8];
@@ -36,102 +36,7 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;  // IEEE division per entry
     }
     if (v_out) store_rows<FMT>(v_out, tile0, lane, n, v);
-    bool bad = false;
-    if constexpr (FMT == CB_F64 || FMT == CB_F32 || FMT == CB_F16) {
-#pragma unroll
-        for (int k = 0; k < M::NG; ++k) {
-            const int r = tile0 + M::group_row(lane, k);
-            uint4 o;
-            if constexpr (FMT == CB_F64) {
-                const double a = v[2 * k], b = v[2 * k + 1];
-                o = make_uint4(lo32(a), hi32(a), lo32(b), hi32(b));
-                bad |= !isfinite(a) || !isfinite(b);
-            } else if constexpr (FMT == CB_F32) {
-                float f[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    f[i] = (float)v[4 * k + i];
-                    bad |= !isfinite(f[i]);
-                }
-                o = make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]),
-                               __float_as_uint(f[3]));
-            } else {
-                uint32_t h[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    h[i] = double_to_half_rne(v[i]);
-                    bad |= (h[i] & 0x7C00u) == 0x7C00u;
-                }
-                o = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
-            }
-            constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
-            if (r < np) *reinterpret_cast<uint4*>(values + (int64_t)r * esz) = o;
-        }
-    } else if constexpr (FMT == CB_FRSZ2_32) {
-        // groups of 4 values; the 8 lanes 8u..8u+7 hold one block
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int r = tile0 + M::group_row(lane, k);
-            uint32_t E = max(max(exp_field(v[4 * k]), exp_field(v[4 * k + 1])),
-                             max(exp_field(v[4 * k + 2]), exp_field(v[4 * k + 3])));
-            E = group_max<3>(E);  // step 1: block maximum
-            uint4 o = make_uint4(frsz2_code<32>(v[4 * k], E), frsz2_code<32>(v[4 * k + 1], E),
-                                 frsz2_code<32>(v[4 * k + 2], E), frsz2_code<32>(v[4 * k + 3], E));
-            if (r < np) {
-                *reinterpret_cast<uint4*>(values + (int64_t)r * 4) = o;
-                if ((lane & 7) == 0) exps[r >> 5] = E;
-            }
-            bad |= E == 0x7FFu;
-        }
-    } else {
-        // 8 values per lane; the 4 lanes 4u..4u+3 hold one block
-        const int r = tile0 + 8 * lane;
-        uint32_t E = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) E = max(E, exp_field(v[q]));
-        E = group_max<2>(E);
-        bad = E == 0x7FFu;
-        if constexpr (FMT == CB_FRSZ2_16) {
-            uint32_t c[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) c[q] = frsz2_code<16>(v[q], E);
-            if (r < np) {
-                *reinterpret_cast<uint4*>(values + (int64_t)r * 2) =
-                    make_uint4(c[0] | c[1] << 16, c[2] | c[3] << 16, c[4] | c[5] << 16, c[6] | c[7] << 16);
-                if ((lane & 3) == 0) exps[r >> 5] = E;
-            }
-        } else {
-            uint32_t c[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) c[q] = frsz2_code<21>(v[q], E);
-            // the 8 codes as a 168-bit stream, code q at bit 21 q
-            uint32_t S[6];
-            S[0] = c[0] | c[1] << 21;
-            S[1] = c[1] >> 11 | c[2] << 10 | c[3] << 31;
-            S[2] = c[3] >> 1 | c[4] << 20;
-            S[3] = c[4] >> 12 | c[5] << 9 | c[6] << 30;
-            S[4] = c[6] >> 2 | c[7] << 19;
-            S[5] = c[7] >> 13;
-            // placed at bit 8 s of block word 5 s (s = lane % 4): W[k] is word 5 s + k
-            const uint32_t sh = 8u * (lane & 3);
-            uint32_t W[6];
-            W[0] = S[0] << sh;
-#pragma unroll
-            for (int k = 1; k < 6; ++k) W[k] = sh ? ((S[k] << sh) | (S[k - 1] >> (32u - sh))) : S[k];
-            // word 5 s + 5 is shared with the next lane of the block
-            const uint32_t next0 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)W[0], 0xF9, 0xF, 0xF, false);
-            if ((lane & 3) != 3) W[5] |= next0;
-            if (r < np) {
-                uint32_t* blk = reinterpret_cast<uint32_t*>(values) + (int64_t)(r >> 5) * 21 + 5 * (lane & 3);
-                if ((lane & 3) == 0) {
-                    blk[0] = W[0];
-                    exps[r >> 5] = E;
-                }
-#pragma unroll
-                for (int k = 1; k < 6; ++k) blk[k] = W[k];
-            }
-        }
-    }
+    const bool bad = encode_tile<FMT>(values, exps, np, tile0, lane, v);
     if (flag && bad) atomicOr(flag, 1);
 }
 
@@ -150,31 +55,6 @@ __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double*
 }
 
 // ----------------------------------------------------------------- CGS projection
-// One wave's columns [c0, c1) of its tile, 8 at a time; the wave's sums for
-// column c are added to red[c - c0].  The loads of the next 8 columns are issued
-// before the current 8 are reduced across the wave.
-template <int FMT, int LM>
-__device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1, int tile0, int lane,
-                                             const double* wv, double* red) {
-    Tile<FMT> t[8];
-    int cols[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) cols[u] = min(c0 + u, c1 - 1);
-    load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
-    for (int c = c0; c < c1; c += 8) {
-        double p[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = t[u].dot(wv);
-        if (c + 8 < c1) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) cols[u] = min(c + 8 + u, c1 - 1);
-            load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
-        }
-        const double sum = wave_sum8(p);  // lane 8u holds column c + u
-        if ((lane & 7) == 0 && c + (lane >> 3) < c1) red[c + (lane >> 3) - c0] += sum;
-    }
-}
-
 // Workgroup (g, y) takes the row groups g, g + G, g + 2G, ... (2048 rows each;
 // G <= kProjectGroups keeps the partials few) and the columns
 // [y cw, (y+1) cw), and writes partials[c * G + g], its sum of D(v_c) * w:
@@ -220,21 +100,6 @@ __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
 }
 
 // ----------------------------------------------------------------- CGS update / x update
-template <int FMT, int U, int LM>
-__device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const double* __restrict__ h,
-                                              int tile0, int lane, double* acc) {
-    for (int c = 0; c < j; c += U) {
-        Tile<FMT> t[U];
-        int cols[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
-        load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
-    }
-}
-
 // w[k] += sign * sum_{c<j} h[c] * D(v_c)[k] over the row groups g, g + G, ...
 // of workgroup g; partials[g] = sum of w[k]^2 over those rows after the update
 // (row groups in order, then the waves in order), if partials != NULL, and

@@ -33,6 +33,11 @@ constexpr int kCounterBytes = 8192;  // ticket counters of the last-workgroup re
 // line plus one line per 32 workgroups
 constexpr int kMaxTicketWorkgroups = (kCounterBytes / 128 - 1) * 32;
 constexpr int kMaxRestart = 512;  // largest restart length m
+// one-workgroup batched solver (batch.hip)
+constexpr int kBatchThreads = 512;
+constexpr int kBatchMaxN = 65536;
+constexpr int kBatchMaxRestart = 104;
+int64_t batch_workspace_bytes(int32_t n, int32_t m, int format);
 
 inline int64_t nblocks(int64_t n) { return (n + kBS - 1) / kBS; }
 inline int64_t padded_rows(int64_t n) { return nblocks(n) * kBS; }

@@ -2,13 +2,16 @@
 //
 // Requests enter a FIFO queue.  A request is admitted when its device
 // footprint (basis columns, CSR arrays, work vectors, reduction partials) fits
-// in what is left of the HBM budget; admitted requests run concurrently, one
-// per lane, each lane a host worker thread with its own HIP stream, so solves
-// of different sizes overlap on the device.  When a solve ends its memory is
-// returned to the budget and the next queued requests are admitted.  Each
-// solve calls the same solver entry point (and so the same kernels with the
-// same reduction order) as a stand-alone cbgmres_solve, so a result does not
-// depend on the mix it ran in.
+// in what is left of the HBM budget; admitted requests run concurrently on a
+// pool of lanes, each lane a host worker thread with its own HIP stream, so
+// solves overlap on the device.  A lane that finds small requests at the head
+// of the queue takes all of them that fit (up to kMaxBatch) and solves them in
+// ONE persistent launch of the one-workgroup batched solver; a large request
+// gets a lane to itself and the multi-workgroup solver.  When a solve ends its
+// memory is returned to the budget and the next queued requests are admitted,
+// while the other lanes keep running.  Which path a request takes depends on
+// its own shape only, and neither path's arithmetic depends on what runs
+// beside it, so a result does not depend on the mix it ran in.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -61,44 +64,122 @@ struct cb_server {
 
 namespace cb {
 
+// Requests up to this size go to the batched one-workgroup solver.
+constexpr int32_t kSmallN = 16384;
+constexpr int kMaxBatch = 512;
+
+static bool is_small(int32_t n, int32_t m) { return n <= kSmallN && m <= kBatchMaxRestart; }
+
+static int64_t al256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
 static int64_t request_bytes(int32_t n, int32_t nnz, int32_t m, int format) {
-    int64_t ws = cbgmres_workspace_bytes(n, m, format);
+    int64_t ws = is_small(n, m) ? batch_workspace_bytes(n, m, format) : cbgmres_workspace_bytes(n, m, format);
     if (ws < 0) return -1;
     // CSR + b + x on the device, plus the solver workspace
-    return ws + (int64_t)(n + 1) * 4 + (int64_t)nnz * 12 + 2 * padded_rows(n) * 8 + 4096;
+    return ws + al256((int64_t)(n + 1) * 4) + al256((int64_t)nnz * 4) + al256((int64_t)nnz * 8) +
+           2 * al256((int64_t)n * 8) + 4096;
+}
+
+// Device copies of a request's inputs inside one allocation, workspace last.
+struct Placed {
+    int64_t rp, ci, va, b, x, ws, total;
+};
+static Placed place(const Request& r, int64_t ws_bytes) {
+    Placed p;
+    p.rp = 0;
+    p.ci = p.rp + al256((int64_t)(r.n + 1) * 4);
+    p.va = p.ci + al256((int64_t)r.nnz * 4);
+    p.b = p.va + al256((int64_t)r.nnz * 8);
+    p.x = p.b + al256((int64_t)r.n * 8);
+    p.ws = p.x + al256((int64_t)r.n * 8);
+    p.total = p.ws + al256(ws_bytes);
+    return p;
+}
+static bool upload(const Request& r, unsigned char* mem, const Placed& p, hipStream_t s) {
+    return hipMemcpyAsync(mem + p.rp, r.row_ptr.data(), (size_t)(r.n + 1) * 4, hipMemcpyHostToDevice, s) ==
+               hipSuccess &&
+           (r.nnz == 0 ||
+            (hipMemcpyAsync(mem + p.ci, r.col.data(), (size_t)r.nnz * 4, hipMemcpyHostToDevice, s) ==
+                 hipSuccess &&
+             hipMemcpyAsync(mem + p.va, r.val.data(), (size_t)r.nnz * 8, hipMemcpyHostToDevice, s) ==
+                 hipSuccess)) &&
+           hipMemcpyAsync(mem + p.b, r.b.data(), (size_t)r.n * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipMemcpyAsync(mem + p.x, r.x.data(), (size_t)r.n * 8, hipMemcpyHostToDevice, s) == hipSuccess;
+}
+static cb_csr csr_at(const Request& r, unsigned char* mem, const Placed& p) {
+    return cb_csr{r.n, r.nnz, reinterpret_cast<int32_t*>(mem + p.rp), reinterpret_cast<int32_t*>(mem + p.ci),
+                  reinterpret_cast<double*>(mem + p.va)};
 }
 
 static int run_request(Request& r, hipStream_t s) {
-    const int n = r.n;
+    const int64_t ws = cbgmres_workspace_bytes(r.n, r.m, r.format);
+    const Placed p = place(r, ws);
     unsigned char* mem = nullptr;
-    const int64_t ws = cbgmres_workspace_bytes(n, r.m, r.format);
-    auto al = [](int64_t x) { return (x + 255) & ~int64_t(255); };
-    const int64_t o_rp = 0;
-    const int64_t o_ci = o_rp + al((int64_t)(n + 1) * 4);
-    const int64_t o_va = o_ci + al((int64_t)r.nnz * 4);
-    const int64_t o_b = o_va + al((int64_t)r.nnz * 8);
-    const int64_t o_x = o_b + al((int64_t)n * 8);
-    const int64_t o_ws = o_x + al((int64_t)n * 8);
-    const int64_t total = o_ws + ws;
-    if (hipMallocAsync(reinterpret_cast<void**>(&mem), (size_t)total, s) != hipSuccess)
-        return fail(CB_ERR_HIP, "device allocation of %lld bytes failed", (long long)total);
+    if (hipMallocAsync(reinterpret_cast<void**>(&mem), (size_t)p.total, s) != hipSuccess)
+        return fail(CB_ERR_HIP, "device allocation of %lld bytes failed", (long long)p.total);
     int st = CB_OK;
-    if (hipMemcpyAsync(mem + o_rp, r.row_ptr.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s) ||
-        hipMemcpyAsync(mem + o_ci, r.col.data(), (size_t)r.nnz * 4, hipMemcpyHostToDevice, s) ||
-        hipMemcpyAsync(mem + o_va, r.val.data(), (size_t)r.nnz * 8, hipMemcpyHostToDevice, s) ||
-        hipMemcpyAsync(mem + o_b, r.b.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) ||
-        hipMemcpyAsync(mem + o_x, r.x.data(), (size_t)n * 8, hipMemcpyHostToDevice, s)) {
+    if (!upload(r, mem, p, s)) {
         st = fail(CB_ERR_HIP, "input copy failed");
     } else {
-        cb_csr A{n, r.nnz, reinterpret_cast<int32_t*>(mem + o_rp), reinterpret_cast<int32_t*>(mem + o_ci),
-                 reinterpret_cast<double*>(mem + o_va)};
-        st = cbgmres_solve(&A, reinterpret_cast<double*>(mem + o_b), reinterpret_cast<double*>(mem + o_x),
-                           r.m, r.tol, r.format, nullptr, mem + o_ws, (size_t)ws, nullptr, 0, &r.result, s);
-        if (hipMemcpyAsync(r.x.data(), mem + o_x, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        const cb_csr A = csr_at(r, mem, p);
+        st = cbgmres_solve(&A, reinterpret_cast<double*>(mem + p.b), reinterpret_cast<double*>(mem + p.x),
+                           r.m, r.tol, r.format, nullptr, mem + p.ws, (size_t)ws, nullptr, 0, &r.result, s);
+        if (hipMemcpyAsync(r.x.data(), mem + p.x, (size_t)r.n * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
             st = fail(CB_ERR_HIP, "result copy failed");
     }
     (void)hipFreeAsync(mem, s);
     (void)hipStreamSynchronize(s);
+    return st;
+}
+
+// Small requests: one allocation for all of them, one batched launch.
+// Statuses land in each request's result.
+static int run_batch(std::vector<std::shared_ptr<Request>>& rs, hipStream_t s) {
+    const int count = (int)rs.size();
+    std::vector<Placed> ps(count);
+    std::vector<int64_t> base(count);
+    int64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        ps[i] = place(*rs[i], batch_workspace_bytes(rs[i]->n, rs[i]->m, rs[i]->format));
+        base[i] = total;
+        total += ps[i].total;
+    }
+    unsigned char* mem = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&mem), (size_t)total, s) != hipSuccess)
+        return fail(CB_ERR_HIP, "device allocation of %lld bytes failed", (long long)total);
+    int st = CB_OK;
+    std::vector<cb_batch_item> items(count);
+    std::vector<cb_result> res(count);
+    for (int i = 0; i < count && st == CB_OK; ++i) {
+        const Request& r = *rs[i];
+        unsigned char* m = mem + base[i];
+        if (!upload(r, m, ps[i], s)) {
+            st = fail(CB_ERR_HIP, "input copy failed");
+            break;
+        }
+        items[i].A = csr_at(r, m, ps[i]);
+        items[i].b = reinterpret_cast<double*>(m + ps[i].b);
+        items[i].x = reinterpret_cast<double*>(m + ps[i].x);
+        items[i].workspace = m + ps[i].ws;
+        items[i].workspace_bytes = (size_t)(ps[i].total - ps[i].ws);
+        items[i].m = r.m;
+        items[i].format = r.format;
+        items[i].tol = r.tol;
+    }
+    if (st == CB_OK) {
+        const int bst = cbgmres_solve_batch(items.data(), count, nullptr, res.data(), s);
+        if (bst == CB_ERR_HIP || bst == CB_ERR_INVALID_ARG || bst == CB_ERR_WORKSPACE) st = bst;
+    }
+    for (int i = 0; i < count && st == CB_OK; ++i)
+        if (hipMemcpyAsync(rs[i]->x.data(), mem + base[i] + ps[i].x, (size_t)rs[i]->n * 8,
+                           hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = fail(CB_ERR_HIP, "result copy failed");
+    (void)hipFreeAsync(mem, s);
+    (void)hipStreamSynchronize(s);
+    for (int i = 0; i < count; ++i) {
+        rs[i]->result = st == CB_OK ? res[i] : cb_result{};
+        rs[i]->result.status = st == CB_OK ? res[i].status : st;
+    }
     return st;
 }
 
@@ -107,7 +188,7 @@ static void worker_main(cb_server* S) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
     for (;;) {
-        std::shared_ptr<Request> r;
+        std::vector<std::shared_ptr<Request>> take;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // FIFO admission: the head of the queue runs once it fits
@@ -120,24 +201,40 @@ static void worker_main(cb_server* S) {
                 continue;
             }
             if (S->charged + S->queue.front()->bytes > (int64_t)S->budget) continue;
-            r = S->queue.front();
-            S->queue.pop_front();
-            S->charged += r->bytes;
-            S->running += 1;
-            r->t_start = S->now();
+            // the head, and with a small head every small request behind it that fits
+            const bool small = is_small(S->queue.front()->n, S->queue.front()->m);
+            while (!S->queue.empty() && (int)take.size() < (small ? kMaxBatch : 1)) {
+                auto& q = S->queue.front();
+                if (is_small(q->n, q->m) != small || S->charged + q->bytes > (int64_t)S->budget) break;
+                S->charged += q->bytes;
+                q->t_start = S->now();
+                take.push_back(q);
+                S->queue.pop_front();
+            }
+            S->running += (int)take.size();
         }
-        int st = run_request(*r, s);
+        int st = CB_OK;
+        if (take.size() == 1 && !is_small(take[0]->n, take[0]->m)) {
+            st = run_request(*take[0], s);
+            if (st == CB_PENDING) st = CB_ERR_HIP;
+            take[0]->result.status = st;
+        } else {
+            run_batch(take, s);
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            r->t_end = S->now();
-            r->status = st == CB_PENDING ? CB_ERR_HIP : st;
-            r->result.status = r->status;
-            S->charged -= r->bytes;
-            S->running -= 1;
-            r->row_ptr.clear(); r->row_ptr.shrink_to_fit();
-            r->col.clear(); r->col.shrink_to_fit();
-            r->val.clear(); r->val.shrink_to_fit();
-            r->b.clear(); r->b.shrink_to_fit();
+            const double t = S->now();
+            for (auto& r : take) {
+                r->t_end = t;
+                r->status = r->result.status == CB_PENDING ? CB_ERR_HIP : r->result.status;
+                r->result.status = r->status;
+                S->charged -= r->bytes;
+                S->running -= 1;
+                r->row_ptr.clear(); r->row_ptr.shrink_to_fit();
+                r->col.clear(); r->col.shrink_to_fit();
+                r->val.clear(); r->val.shrink_to_fit();
+                r->b.clear(); r->b.shrink_to_fit();
+            }
         }
         S->cv.notify_all();
     }
