@@ -182,6 +182,8 @@ __global__ void k_zero(unsigned* __restrict__ c, int words) {
 // Non-temporal basis loads pay off once the columns one pass reads no longer
 // fit in the 256 MB Infinity Cache next to the rest of the working set; below
 // that, the solver's four passes per step over the same columns hit in it.
+constexpr int kResidentWaves = 2048;
+
 static int streams_basis(const BasisView& b, int j) {
     constexpr int64_t kCacheResident = (int64_t)192 << 20;
     return (int64_t)j * (b.col_bytes + 4 * b.exp_stride) > kCacheResident;
@@ -211,11 +213,15 @@ void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* 
                     const int* guard, const Epi& e, hipStream_t s) {
     BasisView b = view_of(V);
     const int G = project_groups(V.n);
-    // column chunks (multiples of 8 columns) until the launch has ~8192 waves
-    int chunks = (8192 + 4 * G - 1) / (4 * G);
+    // Column chunks (multiples of 8 columns) only while the launch has fewer
+    // waves than the GPU keeps resident (~2048 at this kernel's register
+    // use): every workgroup pays a fixed tail (its partial stores and ticket),
+    // so workgroups are made as long as the resident waves allow.
+    int chunks = kResidentWaves / (4 * G);
     chunks = chunks < 1 ? 1 : chunks;
     int max_chunks = (j + 15) / 16;
-    if (max_chunks > kMaxTicketWorkgroups / G) max_chunks = kMaxTicketWorkgroups / G;
+    const int ngroups = (G + kTicketGroup - 1) / kTicketGroup;  // ticket groups per chunk
+    if (max_chunks > kMaxTicketGroups / ngroups) max_chunks = kMaxTicketGroups / ngroups;
     chunks = chunks > max_chunks ? max_chunks : chunks;
     chunks = chunks < 1 ? 1 : chunks;
     int cw = (j + chunks - 1) / chunks;
@@ -225,6 +231,7 @@ void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* 
     Epi ee = e;
     ee.G = G;
     ee.ncols = j;
+    ee.cw = cw;
     const int stream = streams_basis(b, j);
     CB_DISPATCH(fmt, (k_project<F><<<grid, kThreads, 0, s>>>(b, j, w, partials, G, cw, stream, guard, ee)));
 }
@@ -238,6 +245,7 @@ void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const d
     Epi ee = e;
     ee.G = G;
     ee.ncols = 1;
+    ee.cw = 1;
     // with the count on the device, size the policy for the largest count j
     const int stream = streams_basis(b, j);
     CB_DISPATCH(fmt, (k_subtract<F, 4><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials, sign, stream,

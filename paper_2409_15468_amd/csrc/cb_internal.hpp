@@ -29,9 +29,6 @@ constexpr int kSeg = 8;           // rows per thread in the row-segment kernels
 constexpr int kThreads = 256;     // threads per workgroup in the row kernels
 constexpr int kRowsPerWG = kThreads * kSeg;  // 2048 rows = 64 FRSZ2 blocks
 constexpr int kCounterBytes = 8192;  // ticket counters of the last-workgroup reductions
-// workgroups one last-workgroup reduction can serve: one 128-byte top counter
-// line plus one line per 32 workgroups
-constexpr int kMaxTicketWorkgroups = (kCounterBytes / 128 - 1) * 32;
 constexpr int kMaxRestart = 512;  // largest restart length m
 // one-workgroup batched solver (batch.hip)
 constexpr int kBatchThreads = 512;
@@ -76,6 +73,7 @@ inline BasisView view_of(const cb_basis& V) {
 }
 
 // SpMV geometry: lanes per row and rows per workgroup depend on the matrix only.
+constexpr int kSpmvGroups = 1024;
 int spmv_lanes_per_row(int32_t n, int32_t nnz);
 int spmv_groups(int32_t n, int32_t nnz);
 int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz);

@@ -1,15 +1,20 @@
-// Second reduction stage and the solver's per-step decisions, run by the
-// last workgroup of the kernel that produced the per-workgroup partial sums.
+// Second reduction stage and the solver's per-step decisions, run at the end
+// of the kernel that produced the per-workgroup partial sums.
 //
-// Every workgroup writes its partials, then takes a ticket from a device
-// counter; the workgroup that draws the last ticket sums the partials in
-// workgroup-index order (so the result does not depend on which workgroup
-// finished last), stores or applies the sums, and resets the counter for the
-// next launch on the stream.  Partials are written with device-scope (agent)
-// relaxed atomic stores, which are coherent across the XCDs' L2 caches, and
-// each thread waits for its stores to complete before the ticket is drawn; the
-// last workgroup alone then acquires at device scope (one cache invalidate
-// per launch) and reads the partials with ordinary loads.
+// Every workgroup writes its partials (one per column it owns), then takes a
+// ticket from the counter of its group of 32 workgroups.  The workgroup that
+// draws its group's last ticket sums the group's partials per column in
+// workgroup-index order, writes each sum over the partial of the group's first
+// workgroup, and takes a ticket from the top counter; the workgroup that draws
+// the last top ticket sums the group sums in group order (so the result does
+// not depend on which workgroup finished last), stores or applies the sums,
+// and the counters are left at zero for the next launch on the stream.  The
+// reduction is spread over the groups' last workgroups, which run while other
+// groups still stream, so the final workgroup adds only a few values per
+// column.  Partials are written with device-scope (agent) relaxed atomic
+// stores, which are coherent across the XCDs' L2 caches, and each thread waits
+// for its stores to complete before a ticket is drawn; a workgroup that goes
+// on to read other workgroups' partials first acquires at device scope.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,7 +60,8 @@ struct Epi {
     int ncols;             // sums to form
     int G;                 // partials per column (column stride of `partials`)
     double* out;           // EPI_STORE / EPI_REORTH_PROJECT (u)
-    unsigned* counter;     // ticket counters (counter_words(G) words, zero between launches)
+    unsigned* counter;     // ticket counters (kCounterBytes, zero between launches)
+    int cw;                // columns per workgroup chunk (blockIdx.y), multi-column sums
     const double* extra;   // EPI_STEP_CHECK: the SpMV's ||A v||^2 partials
     int extra_G;
     // solver context (modes 1-3)
@@ -75,18 +81,26 @@ namespace dev {
 __device__ __forceinline__ void store_partial(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Sums of partials[c * G + g] over g for the nc columns c0 .. c0+nc-1 (nc <=
-// 256), into lds[c - c0].  tpc = 256 / nc threads share a column: thread s of
-// the column sums g = s, s + tpc, ... in order, then the tpc sums are added in
-// index order.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int G, int c0, int nc,
-                                                double* lds) {
+// For the nc columns c0 .. c0+nc-1 (nc <= 256): lds[i] = sum over k < M of
+// partials[(c0 + i) * G + m0 + k * stride].  tpc = 256 / nc threads share a
+// column: thread s of the column adds k = s, s + tpc, ... in order (eight loads
+// in flight at a time), then the tpc sums are added in index order.
+__device__ __forceinline__ void reduce_range(const double* __restrict__ partials, int G, int m0, int M,
+                                             int stride, int c0, int nc, double* lds) {
     const int tpc = 256 / nc;
     const int t = threadIdx.x;
     double s = 0.0;
     if (t < tpc * nc) {
-        const double* p = partials + (int64_t)(c0 + t / tpc) * G;
-        for (int k = t % tpc; k < G; k += tpc) s += p[k];
+        const double* p = partials + (int64_t)(c0 + t / tpc) * G + m0;
+        int k = t % tpc;
+        for (; k + 7 * tpc < M; k += 8 * tpc) {
+            double q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) q[u] = p[(int64_t)(k + u * tpc) * stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += q[u];
+        }
+        for (; k < M; k += tpc) s += p[(int64_t)k * stride];
     }
     lds[t] = s;
     __syncthreads();
@@ -159,44 +173,59 @@ constexpr int kEpiLds = 3 * (kMaxRestart + 2) > 512 ? 3 * (kMaxRestart + 2) : 51
 
 // Ticket counters: a top counter and one counter per group of 32 workgroups,
 // each in its own 128-byte line (same-address device-scope atomics serialise,
-// so a single counter for ~1000 workgroups costs tens of microseconds).
+// so a single counter for ~1000 workgroups costs tens of microseconds).  A
+// launch may use at most kCounterBytes / 128 - 1 group lines.
 constexpr int kTicketGroup = 32;
 constexpr int kCounterLine = 32;  // unsigned words per 128-byte line
-__host__ __device__ constexpr int counter_words(int groups) {
-    return kCounterLine * (1 + (groups + kTicketGroup - 1) / kTicketGroup);
+constexpr int kMaxTicketGroups = kCounterBytes / 128 - 1;
+
+__device__ __forceinline__ bool draw_last(unsigned* c, unsigned count) {
+    const bool last = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == count - 1;
+    if (last) *c = 0u;
+    return last;
 }
 
-// True in the workgroup that finishes last.  Each workgroup's partial stores
-// complete before its ticket is drawn; the last workgroup of each group of 32
-// then draws a ticket from the top counter.  Counters are reset for the next
-// launch by the workgroups that drew their last tickets.
-__device__ __forceinline__ bool last_workgroup(unsigned* counters) {
-    __shared__ int is_last;
+// The two-level reduction of the partials partials[c * G + g] (g = blockIdx.x
+// < G; the columns of workgroup (g, y) are [y cw, min(ncols, (y+1) cw))).
+// Returns true in the one workgroup that finishes last; there lds[c] (c <
+// min(ncols, 256), columns in chunks of 256 handled by reduce_final) is not yet
+// formed -- reduce_final does that.
+__device__ __forceinline__ bool reduce_tickets(const Epi& e, double* partials, double* lds) {
+    __shared__ int flag;
+    const int G = e.G, ng = (G + kTicketGroup - 1) / kTicketGroup;
+    const int q = blockIdx.x / kTicketGroup;
+    const int m0 = q * kTicketGroup, gsize = min(kTicketGroup, G - m0);
+    const int c0 = blockIdx.y * e.cw, c1 = min(e.ncols, c0 + e.cw);
     __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned g = blockIdx.x + gridDim.x * blockIdx.y, G = gridDim.x * gridDim.y;
-        const unsigned grp = g / kTicketGroup;
-        const unsigned gsize = min((unsigned)kTicketGroup, G - grp * kTicketGroup);
-        const unsigned ngrp = (G + kTicketGroup - 1) / kTicketGroup;
-        unsigned* gc = counters + kCounterLine * (1 + grp);
-        int last = 0;
-        if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
-            *gc = 0u;
-            if (__hip_atomic_fetch_add(counters, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1) {
-                *counters = 0u;
-                last = 1;
-            }
-        }
-        is_last = last;
-    }
+    if (threadIdx.x == 0)
+        flag = draw_last(e.counter + kCounterLine * (1 + blockIdx.y * ng + q), (unsigned)gsize);
     __syncthreads();
-    if (!is_last) return false;
+    if (!flag) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the group's sums, over the partial of its first workgroup
+    for (int a = c0; a < c1; a += 256) {
+        const int nc = min(256, c1 - a);
+        reduce_range(partials, G, m0, gsize, 1, a, nc, lds);
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) store_partial(partials + (int64_t)(a + i) * G + m0, lds[i]);
+        __syncthreads();
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) flag = draw_last(e.counter, gridDim.y * (unsigned)ng);
+    __syncthreads();
+    if (!flag) return false;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return true;
 }
 
-// sum of partials[0 .. G) in a fixed order, valid in thread 0
+// In the last workgroup: lds[i] = the full sum of column a + i, i < nc.
+__device__ __forceinline__ void reduce_final(const Epi& e, const double* partials, int a, int nc, double* lds) {
+    const int ng = (e.G + kTicketGroup - 1) / kTicketGroup;
+    reduce_range(partials, e.G, 0, ng, kTicketGroup, a, nc, lds);
+}
+
+// sum of p[0 .. G) in a fixed order, valid in thread 0
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int G) {
     double t = 0.0;
     for (int k = threadIdx.x; k < G; k += blockDim.x) t += p[k];
@@ -204,13 +233,13 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 }
 
 // Run by every workgroup of the launch after its partials are written
-// (all threads; blockDim.x == 256; at most 2016 workgroups).
-__device__ __forceinline__ void epilogue(const Epi& e, const double* __restrict__ partials, double* lds) {
-    if (!last_workgroup(e.counter)) return;
+// (all threads; blockDim.x == 256).
+__device__ __forceinline__ void epilogue(const Epi& e, double* partials, double* lds) {
+    if (!reduce_tickets(e, partials, lds)) return;
     if ((e.mode == EPI_STORE && e.ncols > 1) || e.mode == EPI_REORTH_PROJECT) {
         for (int c0 = 0; c0 < e.ncols; c0 += 256) {
             const int nc = min(256, e.ncols - c0);
-            reduce_partials(partials, e.G, c0, nc, lds);
+            reduce_final(e, partials, c0, nc, lds);
             for (int i = threadIdx.x; i < nc; i += blockDim.x) {
                 const double u = lds[i];
                 e.out[c0 + i] = u;
@@ -221,7 +250,8 @@ __device__ __forceinline__ void epilogue(const Epi& e, const double* __restrict_
         return;
     }
     // one sum (a squared norm)
-    const double t = sum_partials(partials, e.G);
+    reduce_final(e, partials, 0, 1, lds);
+    const double t = lds[0];
     if (e.mode == EPI_STORE) {
         if (threadIdx.x == 0) e.out[0] = t;
         return;

@@ -51,10 +51,13 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     L.v = take(padded_rows(n) * 8);
     L.vals = take(column_bytes(fmt, n) * (m + 1));
     L.exps = take(exponent_words(fmt, n) * 4 * (m + 1));
-    // partial sums: the basis kernels' groups times columns, or one per SpMV
-    // workgroup (at least 4 rows each)
-    L.part = take(8 * (int64_t)project_groups(n) * (m + 1));
-    L.part_s = take(8 * ((int64_t)n / 4 + 1));  // SpMV partials: at least 4 rows per workgroup
+    // partial sums: the basis kernels' groups times columns, one per row group
+    // of k_sumsq, or one per SpMV workgroup (the IR residual)
+    int64_t np_ = (int64_t)project_groups(n) * (m + 1);
+    if (np_ < row_groups(n)) np_ = row_groups(n);
+    if (np_ < kSpmvGroups) np_ = kSpmvGroups;
+    L.part = take(8 * np_);
+    L.part_s = take(8 * (int64_t)kSpmvGroups);  // SpMV partials: one per SpMV workgroup
     L.total = off;
     return L;
 }

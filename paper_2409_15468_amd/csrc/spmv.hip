@@ -5,7 +5,8 @@
 // row's entries i, i+LPR, ... with FMA in CSR order, then the group sums with a
 // fixed shuffle tree.  LPR is the power of two nearest to half the average row
 // length (4 for the 5- and 7-point stencils), so most lanes own one or two
-// nonzeros and the row's column indices are read as one coalesced run.  The
+// nonzeros and the row's column indices are read as one coalesced run.  At
+// most kSpmvGroups workgroups loop over the blocks of 256/LPR rows; the
 // row-to-workgroup map depends on the matrix only, keeping the norm's
 // reduction order fixed.
 #include "cb_internal.hpp"
@@ -28,21 +29,26 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     constexpr int RPW = 256 / LPR;
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
-    const int row = blockIdx.x * RPW + sub;
-    double s = 0.0;
-    if (row < n) {
-        const int k1 = rp[row + 1];
-        for (int k = rp[row] + li; k < k1; k += LPR) s = fma(val[k], x[ci[k]], s);
-    }
+    const int nblk = (n + RPW - 1) / RPW;
+    double nrm = 0.0;
+    // row blocks blockIdx.x, blockIdx.x + gridDim.x, ... (the grid depends on n only)
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int row = blk * RPW + sub;
+        double s = 0.0;
+        if (row < n) {
+            const int k1 = rp[row + 1];
+            for (int k = rp[row] + li; k < k1; k += LPR) s = fma(val[k], x[ci[k]], s);
+        }
 #pragma unroll
-    for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-    double out = 0.0;
-    if (row < n && li == 0) {
-        out = mode ? b[row] - s : s;
-        y[row] = out;
+        for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+        if (row < n && li == 0) {
+            const double out = mode ? b[row] - s : s;
+            y[row] = out;
+            nrm = fma(out, out, nrm);
+        }
     }
     if (partials) {
-        double t = block_sum<256>(out * out);
+        const double t = block_sum<256>(nrm);
         if (threadIdx.x == 0) partials[blockIdx.x] = t;
     }
 }
@@ -54,9 +60,12 @@ int spmv_lanes_per_row(int32_t n, int32_t nnz) {
     return lpr;
 }
 
+// Workgroups of the SpMV: one per block of rows up to kSpmvGroups, which then
+// loop over blocks; few partial sums keep their consumer's reduction short.
 int spmv_groups(int32_t n, int32_t nnz) {
     const int rpw = 256 / spmv_lanes_per_row(n, nnz);
-    return (int)(((int64_t)n + rpw - 1) / rpw);
+    const int64_t blocks = ((int64_t)n + rpw - 1) / rpw;
+    return (int)(blocks < kSpmvGroups ? blocks : kSpmvGroups);
 }
 
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,

@@ -143,3 +143,16 @@ def test_iterative_refinement_precision_form():
     assert res["restarts"] == ref.outer
     assert within_2pct(res["iterations"], ref.iterations)
     assert np.linalg.norm(x - ref64.x) / np.linalg.norm(ref64.x) < 1e-10
+
+
+def test_tall_system_short_restart():
+    """n = 5e6 with GMRES(1): the norm of b uses one partial per 2048-row group
+    (2442 of them), more than the projection partials of a restart length of
+    1 need; the workspace holds both."""
+    n = 5_000_000
+    A = synth.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.full(n, 2.0))
+    b = np.random.default_rng(9).standard_normal(n)
+    assert cb.cbgmres_workspace_bytes(n, 1, "float64") >= 8 * ((n + 2047) // 2048)
+    res, x, _ = gpu_solve(A, b, 1, 1e-12, "float64")
+    assert res["converged"] and res["iterations"] == 1
+    np.testing.assert_allclose(x, b / 2, rtol=1e-13)
