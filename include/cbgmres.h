@@ -145,15 +145,16 @@ int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, voi
                    size_t work_bytes, void* stream);
 
 /* Classical Gram-Schmidt update with decompression fused in (Fig. 1 step 5,
- * second half, and step 6): w[k] -= sum_{i<j} h[i] * D(v_i)[k] (each row's
- * correction summed over i in order, then subtracted), and, if norm2 is
- * non-NULL, *norm2 = ||w||^2 after the update (device double).
+ * second half, and step 6): w[k] -= sum_{i<j} h[i] * D(v_i)[k] (1 <= j <= 513;
+ * each row's correction summed over i in order, then subtracted), and, if
+ * norm2 is non-NULL, *norm2 = ||w||^2 after the update (device double).
  * Asynchronous. */
 int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, double* norm2,
                     void* work, size_t work_bytes, void* stream);
 
 /* Solution update with decompression fused in (Fig. 1 step 17):
- * x[k] += sum_{i<j} y[i] * D(v_i)[k].  y: device float64[j].  Asynchronous. */
+ * x[k] += sum_{i<j} y[i] * D(v_i)[k] (1 <= j <= 513).  y: device float64[j].
+ * Asynchronous. */
 int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream);
 
 /* ======================================================================

@@ -190,6 +190,8 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
                     void* work, size_t work_bytes, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !w || !h) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (j > kMaxRestart + 1)
+        return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     if (norm2 && (!work || (int64_t)work_bytes < reduce_workspace_bytes(V->n, 1, 0)))
         return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes",
                     (long long)reduce_workspace_bytes(V->n, 1, 0));
@@ -204,6 +206,8 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
 int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !y || !x) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (j > kMaxRestart + 1)
+        return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     launch_subtract(V->format, *V, j, nullptr, y, x, nullptr, nullptr, +1, Epi{}, (hipStream_t)stream);
     CB_HIP(hipGetLastError());
     return CB_OK;

@@ -25,13 +25,13 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
                                                     const double* w, const double* __restrict__ divisor,
                                                     double* v_out, int32_t* __restrict__ flag,
                                                     const int* __restrict__ guard) {
-    if (guard && *guard == 0) return;
+    if (guard && ld_ctl(guard) == 0) return;
     const int lane = threadIdx.x & 63;
     const int tile0 = blockIdx.x * kRowsPerWG + (threadIdx.x >> 6) * kTile;
     double v[8];
     load_rows<FMT>(w, tile0, lane, n, v);
     if (divisor) {
-        const double d = *divisor;
+        const double d = ld_ctl(divisor);
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;  // IEEE division per entry
     }
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ partials, int G, int cw,
                                                       int stream, const int* __restrict__ guard, Epi e) {
-    if (guard && *guard == 0) return;
+    if (guard && ld_ctl(guard) == 0) return;
     __shared__ double red[kThreads / 64][kMaxRestart + 1];
     __shared__ double elds[kEpiLds];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,9 +110,13 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
                                                        double* __restrict__ w,
                                                        double* __restrict__ partials, int sign, int stream,
                                                        const int* __restrict__ guard, Epi e) {
-    if (guard && *guard == 0) return;
-    if (jdev) j = *jdev;
+    if (guard && ld_ctl(guard) == 0) return;
+    if (jdev) j = ld_ctl(jdev);
     __shared__ double elds[kEpiLds];
+    // the coefficients (written by an earlier kernel), read once into LDS
+    __shared__ double hc[kMaxRestart + 1];
+    for (int i = threadIdx.x; i < j; i += kThreads) hc[i] = ld_ctl(&h[i]);
+    __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ngroups = row_groups_dev(V.np);
     double nrm = 0.0;
@@ -123,11 +127,11 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
         const bool full = tile0 + kTile <= V.np;
         if (stream) {
-            if (full) subtract_tile<FMT, U, kFull | kStream>(V, j, h, tile0, lane, acc);
-            else subtract_tile<FMT, U, kStream>(V, j, h, tile0, lane, acc);
+            if (full) subtract_tile<FMT, U, kFull | kStream>(V, j, hc, tile0, lane, acc);
+            else subtract_tile<FMT, U, kStream>(V, j, hc, tile0, lane, acc);
         } else {
-            if (full) subtract_tile<FMT, U, kFull>(V, j, h, tile0, lane, acc);
-            else subtract_tile<FMT, U, 0>(V, j, h, tile0, lane, acc);
+            if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
+            else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
         }
         double wv[8];
         load_rows<FMT>(w, tile0, lane, V.n, wv);
@@ -151,12 +155,12 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int G,
                                                 double* __restrict__ out, int op,
                                                 const int* __restrict__ guard) {
-    if (guard && *guard == 0) return;
+    if (guard && ld_ctl(guard) == 0) return;
     const int c = blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < G; i += 256) s += partials[(int64_t)c * G + i];
     s = block_sum<256>(s);
-    if (threadIdx.x == 0) out[c] = op ? out[c] + s : s;
+    if (threadIdx.x == 0) out[c] = op ? ld_ctl(&out[c]) + s : s;
 }
 
 __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {

@@ -343,6 +343,19 @@ __device__ void batch_solve(const BatchItem& it, const BatchOpts& o, cb_result* 
     __syncthreads();
 }
 
+// A descriptor, read with control loads (the same device addresses may have
+// held an earlier launch's descriptors).
+__device__ __forceinline__ BatchItem load_item(const BatchItem* p) {
+    static_assert(sizeof(BatchItem) % 8 == 0, "descriptor size");
+    uint64_t raw[sizeof(BatchItem) / 8];
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(BatchItem) / 8); ++k) raw[k] = ld_ctl(src + k);
+    BatchItem it;
+    __builtin_memcpy(&it, raw, sizeof(BatchItem));
+    return it;
+}
+
 // Persistent over the batch: each workgroup takes the next system until the
 // list is exhausted.  *next must read 0 at launch.
 __global__ __launch_bounds__(kBT) void k_batch(const BatchItem* __restrict__ items, int count,
@@ -354,7 +367,7 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchItem* __restrict__ ite
         const int i = S.item;
         __syncthreads();
         if (i >= count) return;
-        const BatchItem it = items[i];
+        const BatchItem it = load_item(items + i);
         switch (it.format) {
         case CB_F64: batch_solve<CB_F64>(it, o, results + i, S); break;
         case CB_F32: batch_solve<CB_F32>(it, o, results + i, S); break;

@@ -104,5 +104,10 @@ void launch_reduce(const double* partials, int G, int ncols, double* out, int op
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
                  int mode, const int* guard, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+// Column col := Q(w / *divisor) and y = A (w / *divisor), ||y||^2 partials
+// (spmv_groups of them); flag (device, required) set on a non-finite store.
+void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, const double* w,
+                       const double* divisor, double* y, double* partials, int32_t* flag, const int* guard,
+                       hipStream_t s);
 
 }  // namespace cb

@@ -82,25 +82,29 @@ __device__ __forceinline__ void store_partial(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // For the nc columns c0 .. c0+nc-1 (nc <= 256): lds[i] = sum over k < M of
-// partials[(c0 + i) * G + m0 + k * stride].  tpc = 256 / nc threads share a
-// column: thread s of the column adds k = s, s + tpc, ... in order (eight loads
-// in flight at a time), then the tpc sums are added in index order.
+// partials[(c0 + i) * G + m0 + k * stride].  tpc threads share a column (the
+// fewest, up to 256 / nc, that leave each at most 8 loads per batch): thread s
+// of the column issues the loads of k = s, s + tpc, ..., s + 7 tpc together
+// and adds them in order, batch after batch; then the tpc sums are added in
+// index order.  The order depends on (M, nc) only.
 __device__ __forceinline__ void reduce_range(const double* __restrict__ partials, int G, int m0, int M,
                                              int stride, int c0, int nc, double* lds) {
-    const int tpc = 256 / nc;
+    int tpc = 1;
+    while (tpc * 2 <= 256 / nc && tpc * 8 < M) tpc *= 2;
     const int t = threadIdx.x;
     double s = 0.0;
     if (t < tpc * nc) {
         const double* p = partials + (int64_t)(c0 + t / tpc) * G + m0;
-        int k = t % tpc;
-        for (; k + 7 * tpc < M; k += 8 * tpc) {
+        for (int k = t % tpc; k < M; k += 8 * tpc) {
             double q[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) q[u] = p[(int64_t)(k + u * tpc) * stride];
+            for (int u = 0; u < 8; ++u) {
+                const int kk = k + u * tpc;
+                q[u] = kk < M ? p[(int64_t)kk * stride] : 0.0;
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += q[u];
         }
-        for (; k < M; k += tpc) s += p[(int64_t)k * stride];
     }
     lds[t] = s;
     __syncthreads();
@@ -118,7 +122,7 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ partials
 // Givens rotations, implicit residual, end-of-cycle decision.  Called by all
 // threads of one workgroup; H column j, cs and sn are staged in LDS.
 __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, double* lds) {
-    State& s = *e.st;
+    volatile State& s = *e.st;
     const int j = e.j;
     double* h = e.H + (int64_t)j * (e.m + 1);
     double* lh = lds;                // j + 2 entries
@@ -152,8 +156,9 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
         e.sn[j] = sn;
         lh[j] = rho;
         lh[j + 1] = 0.0;
-        e.g[j + 1] = -sn * e.g[j];
-        e.g[j] = c * e.g[j];
+        const double gj = ld_ctl(&e.g[j]);
+        e.g[j + 1] = -sn * gj;
+        e.g[j] = c * gj;
         s.iters += 1;
         s.steps = j + 1;
         s.gabs = fabs(e.g[j + 1]);
@@ -262,7 +267,7 @@ __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double*
     __shared__ int do_finish, bd;
     __shared__ double hn_s;
     if (threadIdx.x == 0) {
-        State& s = *e.st;
+        volatile State& s = *e.st;
         do_finish = 0;
         bd = 0;
         s.hn2 = t;

@@ -6,6 +6,17 @@
 namespace cb {
 namespace dev {
 
+// Load of a control word -- a guard flag, a step count, a divisor, a solver
+// scalar -- that an earlier kernel on the stream or another workgroup wrote:
+// a device-scope atomic load.  Such words sit at addresses every workgroup
+// reads, which the compiler would otherwise load through the scalar cache;
+// that cache is not kept coherent with writes of other kernels when kernels
+// of other streams run beside this one.
+template <class T>
+__device__ __forceinline__ T ld_ctl(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);

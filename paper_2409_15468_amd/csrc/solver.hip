@@ -5,11 +5,13 @@
 // 7), breakdown (step 12), the Givens rotations and the implicit residual
 // (steps 16-17), the end of a cycle -- is taken on the GPU, by the last
 // workgroup of the kernel whose reduction it needs (epilogue.hpp), and written
-// to a control block in device memory.  A step is six launches: SpMV (+ its
-// norm), projection (+ h), update (+ norm and step 7 test), the second
-// projection and update when step 7 asks for them (+ breakdown test and Givens
-// rotation), and the normalise-and-store of the next basis vector; the SpMV's
-// norm is summed by the first update's last workgroup.  The host
+// to a control block in device memory.  A step is five launches: the
+// normalise-and-store of the step's basis vector fused with the SpMV on it
+// (+ its norm), projection (+ h), update (+ norm and step 7 test), and the
+// second projection and update when step 7 asks for them (+ breakdown test
+// and Givens rotation); the SpMV's norm is summed by the first update's last
+// workgroup.  w alternates between two buffers, since the fused kernel reads
+// the previous w at other rows while it writes the new one.  The host
 // enqueues a whole cycle of m steps without waiting; kernels of steps after
 // the cycle has ended read the control block and return at once.  The host
 // waits once per cycle, after the explicit residual of the restart (step 1 /
@@ -28,7 +30,7 @@ namespace cb {
 using namespace dev;
 
 struct Layout {
-    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, v, vals, exps, part, part_s, total;
+    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, w2, vals, exps, part, part_s, total;
 };
 
 static int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -48,7 +50,7 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     L.y = take((int64_t)m * 8);
     L.hist = take((int64_t)m * 8);
     L.w = take(padded_rows(n) * 8);
-    L.v = take(padded_rows(n) * 8);
+    L.w2 = take(padded_rows(n) * 8);
     L.vals = take(column_bytes(fmt, n) * (m + 1));
     L.exps = take(exponent_words(fmt, n) * 4 * (m + 1));
     // partial sums: the basis kernels' groups times columns, one per row group
@@ -78,7 +80,7 @@ __global__ void k_init(State* st, int32_t* flag, unsigned* counter, double tol, 
     for (int i = threadIdx.x; i < kCounterBytes / 4; i += blockDim.x) counter[i] = 0u;
     if (threadIdx.x != 0) return;
     State z = {};
-    z.nb = sqrt(st->r2);
+    z.nb = sqrt(ld_ctl(&st->r2));
     z.tol_abs = tol * z.nb;
     z.eta = eta;
     z.max_iters = max_iters;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void k_cycle_begin(State* st, const int32_t* f
     for (int k = t; k < G; k += blockDim.x) r2 += partials[k];
     r2 = block_sum<256>(r2);
     if (t == 0) {
-        State& s = *st;
+        volatile State& s = *st;
         s.prev_steps = s.steps;
         s.steps = 0;
         s.active = 0;
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(256) void k_cycle_begin(State* st, const int32_t* f
         s.beta = sqrt(s.r2);
         s.rel = s.beta / s.nb;
         go = 0;
-        if (!isfinite(s.beta) || *flag) {
+        if (!isfinite(s.beta) || ld_ctl(flag)) {
             s.stop = 1;
             s.status = CB_ERR_NONFINITE;
         } else if (s.beta <= s.tol_abs) {
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(256) void k_cycle_begin(State* st, const int32_t* f
     }
     __syncthreads();
     if (go)
-        for (int i = t; i <= m; i += blockDim.x) g[i] = i == 0 ? st->beta : 0.0;
+        for (int i = t; i <= m; i += blockDim.x) g[i] = i == 0 ? ld_ctl(&st->beta) : 0.0;
 }
 
 // Step 17: back-substitution R y = g over the cycle's steps, by columns: y_i
@@ -144,20 +146,23 @@ __global__ __launch_bounds__(256) void k_backsolve(State* st, const double* __re
                                                    int m, double col_bytes) {
     __shared__ double rhs[kMaxRestart];
     __shared__ double yi;
-    const int k1 = st->steps;
+    const int k1 = ld_ctl(&st->steps);
     for (int i = threadIdx.x; i < k1; i += blockDim.x) rhs[i] = g[i];
     __syncthreads();
     for (int i = k1 - 1; i >= 0; --i) {
         const double* col = H + (int64_t)i * (m + 1);
         if (threadIdx.x == 0) {
-            yi = rhs[i] / col[i];
+            yi = rhs[i] / ld_ctl(&col[i]);
             y[i] = yi;
         }
         __syncthreads();
         for (int r = threadIdx.x; r < i; r += blockDim.x) rhs[r] -= col[r] * yi;
         __syncthreads();
     }
-    if (threadIdx.x == 0) st->basis_bytes += (double)k1 * col_bytes;
+    if (threadIdx.x == 0) {
+        volatile State& s = *st;
+        s.basis_bytes = s.basis_bytes + (double)k1 * col_bytes;
+    }
 }
 
 __global__ void k_axpy(double* __restrict__ x, const double* __restrict__ d, int n) {
@@ -222,7 +227,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     double* y = W.at<double>(W.L.y);
     double* hist = W.at<double>(W.L.hist);
     double* w = W.at<double>(W.L.w);
-    double* v = W.at<double>(W.L.v);
+    double* w2 = W.at<double>(W.L.w2);
     double* part = W.at<double>(W.L.part);
     double* part_s = W.at<double>(W.L.part_s);
     const int Gs = spmv_groups(n, A.nnz);
@@ -276,31 +281,34 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                     history_host[recorded++] = hh[k] / hs->nb;
             }
             if (hs->stop) break;
-            // v_1 = r / beta, V_1 = Q(v_1)
-            launch_store(fmt, V, 0, w, &st->beta, v, flag, active, s);
+            double* wc = w;   // the current w (the residual r first)
+            double* wn = w2;  // the buffer the next SpMV writes
             for (int j = 0; j < m; ++j) {
                 double* hcol = H + (int64_t)j * (m + 1);
-                // w = A v; its ||w||^2 partials go to the first update's epilogue
-                launch_spmv(A, v, nullptr, w, part_s, 0, active, s);
+                // v_j = w / (beta or h_{j,j-1}), V_j = Q(v_j), w = A v_j; its
+                // ||w||^2 partials go to the first update's epilogue
+                launch_spmv_store(fmt, A, V, j, wc, j == 0 ? &st->beta : &st->hn, wn, part_s, flag, active, s);
+                double* t = wc;
+                wc = wn;
+                wn = t;
                 Epi eh = sum_e;          // h_{1:j+1,j}
                 eh.out = hcol;
-                launch_project(fmt, V, j + 1, w, part, active, eh, s);
+                launch_project(fmt, V, j + 1, wc, part, active, eh, s);
                 Epi ec = step_e;         // omega, ||w||, step 7 test, maybe Givens
                 ec.mode = EPI_STEP_CHECK;
                 ec.j = j;
                 ec.extra = part_s;
                 ec.extra_G = Gs;
-                launch_subtract(fmt, V, j + 1, nullptr, hcol, w, part, active, -1, ec, s);
+                launch_subtract(fmt, V, j + 1, nullptr, hcol, wc, part, active, -1, ec, s);
                 Epi eu = step_e;         // u = V^T w, h += u
                 eu.mode = EPI_REORTH_PROJECT;
                 eu.out = u;
                 eu.j = j;
-                launch_project(fmt, V, j + 1, w, part, reorth, eu, s);
+                launch_project(fmt, V, j + 1, wc, part, reorth, eu, s);
                 Epi ef = step_e;         // ||w||, breakdown test, Givens
                 ef.mode = EPI_REORTH_FINISH;
                 ef.j = j;
-                launch_subtract(fmt, V, j + 1, nullptr, u, w, part, reorth, -1, ef, s);
-                if (j + 1 < m) launch_store(fmt, V, j + 1, w, &st->hn, v, flag, active, s);
+                launch_subtract(fmt, V, j + 1, nullptr, u, wc, part, reorth, -1, ef, s);
             }
             k_backsolve<<<1, 256, 0, s>>>(st, H, g, y, m, cbytes);
             launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, Epi{}, s);

@@ -12,10 +12,84 @@
 #include "cb_internal.hpp"
 #include "epilogue.hpp"
 #include "reduce.hpp"
+#include "tiles.hpp"
 
 namespace cb {
 
 using namespace dev;
+
+// y = A x over the row blocks blk = blockIdx.x, +gridDim.x, ... of 256/LPR rows
+// (x[c] read as xs[c] / d when DIV: the normalised vector formed on the fly);
+// returns this thread's share of ||y||^2.
+template <int LPR, bool DIV>
+__device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                            const double* __restrict__ val, const double* __restrict__ xs,
+                                            double d, double* __restrict__ y) {
+    constexpr int RPW = 256 / LPR;
+    const int sub = threadIdx.x / LPR;
+    const int li = threadIdx.x % LPR;
+    const int nblk = (n + RPW - 1) / RPW;
+    double nrm = 0.0;
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int row = blk * RPW + sub;
+        double s = 0.0;
+        if (row < n) {
+            const int k1 = rp[row + 1];
+            for (int k = rp[row] + li; k < k1; k += LPR) {
+                const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
+                s = fma(val[k], xv, s);
+            }
+        }
+#pragma unroll
+        for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+        if (row < n && li == 0) {
+            y[row] = s;
+            nrm = fma(s, s, nrm);
+        }
+    }
+    return nrm;
+}
+
+// Fig. 1 steps 13-14 of the previous step fused with steps 3-4 of this one:
+// column col of the basis := Q(w / d) (IEEE division per entry, as k_store),
+// and y = A (w / d) with the quotients formed again where the SpMV reads them
+// (the same division, so the same values), ||y||^2 per workgroup.  The encode
+// runs over the 2048-row groups g = blockIdx.x, +gridDim.x, ...; the SpMV over
+// the row blocks.  w is only read, y is another buffer.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const double* __restrict__ val,
+                                                    int lpr, const double* __restrict__ w,
+                                                    const double* __restrict__ divisor, double* __restrict__ y,
+                                                    double* __restrict__ partials, unsigned char* __restrict__ values,
+                                                    uint32_t* __restrict__ exps, int32_t* __restrict__ flag,
+                                                    const int* __restrict__ guard) {
+    if (guard && ld_ctl(guard) == 0) return;
+    const double d = ld_ctl(divisor);
+    const int lane = threadIdx.x & 63;
+    bool bad = false;
+    for (int g = blockIdx.x; g * kRowsPerWG < np; g += gridDim.x) {
+        const int tile0 = g * kRowsPerWG + (threadIdx.x >> 6) * kTile;
+        double v[8];
+        load_rows<FMT>(w, tile0, lane, n, v);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = v[q] / d;
+        bad |= encode_tile<FMT>(values, exps, np, tile0, lane, v);
+    }
+    if (bad) atomicOr(flag, 1);
+    double nrm;
+    switch (lpr) {
+    case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, y); break;
+    case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, y); break;
+    case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, y); break;
+    case 8: nrm = spmv_rows<8, true>(n, rp, ci, val, w, d, y); break;
+    case 16: nrm = spmv_rows<16, true>(n, rp, ci, val, w, d, y); break;
+    case 32: nrm = spmv_rows<32, true>(n, rp, ci, val, w, d, y); break;
+    default: nrm = spmv_rows<64, true>(n, rp, ci, val, w, d, y); break;
+    }
+    const double t = block_sum<256>(nrm);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
 
 template <int LPR>
 __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
@@ -25,7 +99,7 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
                                               const double* __restrict__ b, double* __restrict__ y,
                                               double* __restrict__ partials, int mode,
                                               const int* __restrict__ guard) {
-    if (guard && *guard == 0) return;
+    if (guard && ld_ctl(guard) == 0) return;
     constexpr int RPW = 256 / LPR;
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
@@ -87,6 +161,31 @@ void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, d
         CB_SPMV_CASE(64)
     }
 #undef CB_SPMV_CASE
+}
+
+void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, const double* w,
+                       const double* divisor, double* y, double* partials, int32_t* flag, const int* guard,
+                       hipStream_t s) {
+    const BasisView b = view_of(V);
+    unsigned char* vals = static_cast<unsigned char*>(V.values) + (int64_t)col * b.col_bytes;
+    uint32_t* ex = V.exps ? V.exps + (int64_t)col * b.exp_stride : nullptr;
+    const int lpr = spmv_lanes_per_row(A.n, A.nnz);
+    const int G = spmv_groups(A.n, A.nnz);
+#define CB_SS_CASE(F)                                                                                  \
+    case F:                                                                                            \
+        k_spmv_store<F><<<G, 256, 0, s>>>(A.n, b.np, A.row_ptr, A.col, A.val, lpr, w, divisor, y,      \
+                                          partials, vals, ex, flag, guard);                            \
+        break;
+    switch (fmt) {
+        CB_SS_CASE(CB_F64)
+        CB_SS_CASE(CB_F32)
+        CB_SS_CASE(CB_F16)
+        CB_SS_CASE(CB_FRSZ2_16)
+        CB_SS_CASE(CB_FRSZ2_21)
+        default:
+        CB_SS_CASE(CB_FRSZ2_32)
+    }
+#undef CB_SS_CASE
 }
 
 }  // namespace cb

@@ -75,3 +75,42 @@ def test_argument_errors_without_device_work():
     assert L.cb_basis_load(C.byref(V), 0, 1, None) == cb.CB_ERR_INVALID_ARG
     for s in range(10):
         assert L.cb_status_string(s)
+
+
+def test_column_count_limits_without_device_work():
+    """The projection, update and combine take at most 513 columns (their
+    per-column sums and coefficients live in LDS); more is rejected before any
+    launch.  Pointers here are never dereferenced."""
+    L = cb.lib()
+    V = cb.cb_basis(5, 100, 600, 0, 256, 256)
+    assert L.cb_cgs_project(C.byref(V), 514, 256, 256, 256, 1 << 30, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_subtract(C.byref(V), 514, 256, 256, None, None, 0, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_basis_combine(C.byref(V), 514, 256, 256, None) == cb.CB_ERR_INVALID_ARG
+
+
+def test_batch_arguments_without_device_work():
+    L = cb.lib()
+    assert cb.cbgmres_batch_max_n() >= 16384 and cb.cbgmres_batch_max_restart() >= 100
+    assert cb.cbgmres_batch_workspace_bytes(0, 10, "float64") == -1
+    assert cb.cbgmres_batch_workspace_bytes(100, 0, "float64") == -1
+    assert cb.cbgmres_batch_workspace_bytes(100, 10, 9) == -1
+    need = cb.cbgmres_batch_workspace_bytes(1000, 30, "frsz2_21")
+    assert need >= 31 * cb.cb_basis_column_bytes("frsz2_21", 1000) + 2 * 8 * 1000
+    res = (cb.cb_result * 1)()
+    item = (cb.cb_batch_item * 1)()
+    item[0].A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    item[0].b, item[0].x, item[0].workspace = 256, 256, 256
+    item[0].workspace_bytes = need
+    item[0].m, item[0].format, item[0].tol = 30, 4, 1e-8
+    item[0].m = cb.cbgmres_batch_max_restart() + 1
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_INVALID_ARG
+    item[0].m = 30
+    item[0].workspace_bytes = need - 1
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_WORKSPACE
+    item[0].workspace_bytes = need
+    item[0].workspace = 257  # not 256-byte aligned
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_WORKSPACE
+    item[0].workspace = 256
+    item[0].tol = 0.0
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cbgmres_solve_batch(item, 0, None, res, None) == cb.CB_OK
