@@ -11,8 +11,18 @@ frsz2_32 columns of 2^24 rows, the tall-skinny test basis, seed 2), timed with
 HIP events on the stream it runs on; algorithmic bytes per launch =
 101 * 2^24 * 4.125 (codes + block exponents) + 8 * 2^24 (w).
 
-CPU baseline: the FP64 oracle, single thread, on the first 40 Arnoldi steps of
+`traffic` is the HBM bytes per launch of that kernel from the committed
+FETCH_SIZE / WRITE_SIZE counter summary under profiles/ (scaled by the same
+counters' reading for a 1 GiB copy), reported only while the kernel sources
+hash to the value recorded there; otherwise null.
+
+CPU baseline: the FP64 oracle, single thread, on the first 80 Arnoldi steps of
 the same solve, scaled to the whole solve by basis-column work.
+
+Other workloads (--workload): `serving` runs the seeded request stream through
+the continuous-batching server (p50/p99 latency, solves/s); `precision` runs
+FP64 iterative refinement around a frsz2_16-basis GMRES(100) against the
+float64-basis solve on the 2^22-row banded system.
 
 Prints one JSON line.
 """
@@ -29,6 +39,38 @@ import numpy as np  # noqa: E402
 
 METRIC = "CB-GMRES time-to-1e-10 residual, frsz2 vs fp64 basis; decompress+CGS HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_project_frsz2_32_microbench_2p24x101.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2409_15468_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_project<frsz2_32> launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, or None if the kernel sources changed since
+    the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -105,7 +147,7 @@ def microbench(cb, torch, n, ncols, reps, formats):
     return out
 
 
-def cpu_baseline(s, gpu_iters, gpu_cycles, m, sample_steps=40):
+def cpu_baseline(s, gpu_iters, gpu_cycles, m, sample_steps=80):
     """The oracle on the first `sample_steps` Arnoldi steps of the same solve,
     scaled to the whole solve by the Gram-Schmidt work, which dominates the
     oracle's time: step j of a cycle costs in proportion to its j + 1 basis
@@ -342,8 +384,9 @@ def main():
                         [f for f in args.micro_formats.split(",") if f])
         z = mb.get("frsz2_32")
         if z:
+            traffic = measured_traffic() if args.micro_rows == 1 << 24 else None
             rec["roofline"] = {"bound": "hbm", "achieved": z["dot_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": z["dot_GBs"] / HBM_PEAK_GBS, "traffic": None,
+                               "frac": z["dot_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                                "kernel": "k_project<frsz2_32> (fused decompress + CGS projection)",
                                "per_launch_bytes": 101 * args.micro_rows * z["bytes_per_value"] + 8 * args.micro_rows,
                                "avg_launch_s": z["dot_s"]}
