@@ -181,6 +181,8 @@ def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
     mats = {}
     systems = []
     for r in reqs:
+        if r.rid % 64 == 0:
+            log(f"serving: building request {r.rid}/{count}")
         key = (r.dim, r.N)
         if key not in mats:
             mats[key] = synth.convection_diffusion(r.N, r.dim, (20.0, 0.0) if r.dim == 2 else (10.0, 5.0, 2.0))
@@ -193,8 +195,12 @@ def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
     done = {}
     t0 = time.perf_counter()
     nxt = 0
+    last_log = 0.0
     while nxt < count or pending:
         now = time.perf_counter() - t0
+        if now - last_log > 5.0:
+            log(f"serving: t={now:.1f}s submitted {nxt}, finished {len(done)}")
+            last_log = now
         while nxt < count and reqs[nxt].arrival_s <= now:
             A, b = systems[nxt]
             tk = server.submit(A.row_ptr, A.col, A.val, b, reqs[nxt].m, reqs[nxt].tol, reqs[nxt].fmt)
@@ -297,11 +303,16 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-lanes", type=int, default=8)
+    ap.add_argument("--serve-hw-queues", type=int, default=0,
+                    help="hardware queues per process for the serving run (GPU_MAX_HW_QUEUES, <= 32; "
+                         "0: the runtime default); streams beyond the queue count share queues")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serving" and args.serve_hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.serve_hw_queues))
     import torch
 
     import paper_2409_15468_amd as cb
@@ -317,7 +328,7 @@ def main():
                "config": {"workload": f"{args.serve_count} seeded convection-diffusion solve requests, Poisson "
                                       f"arrivals {args.serve_rate}/s, n 32^2..128^3, formats f32/frsz2_16/21/32, "
                                       f"tol 1e-12..1e-8, m 30..100, HBM budget {args.serve_budget_gb} GB"},
-               "serving": sv}
+               "serving": dict(sv, hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"))}
         print(json.dumps(rec), flush=True)
         return
     if args.workload == "precision":

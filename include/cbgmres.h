@@ -285,18 +285,22 @@ int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_opti
  * Requests are admitted while their device footprint fits in the HBM budget
  * (basis n*(m+1) stored bytes + CSR + work vectors); later arrivals wait in
  * FIFO order and are admitted as earlier solves finish and release memory.
- * Admitted solves run concurrently on a pool of lanes (host threads, each
- * with its own HIP stream).  Small requests (n <= 16384, m <=
- * cbgmres_batch_max_restart()) at the head of the queue are taken together and
- * solved in one persistent launch of the batched solver (cbgmres_solve_batch);
- * larger ones run cbgmres_solve on a lane of their own.  The path depends on a
- * request's shape only and neither path's arithmetic depends on the other
- * requests, so a result is the same alone and in any mix.
+ * Admitted solves run concurrently on lanes (host threads, each with its own
+ * HIP stream).  Small requests (n <= 16384, m <= cbgmres_batch_max_restart())
+ * go to two batch lanes: a free batch lane takes every small request waiting
+ * (in arrival order, as far as the budget allows) and solves them in one
+ * persistent launch of the batched solver (cbgmres_solve_batch).  Larger
+ * requests go, in arrival order, to the solve lanes, each running
+ * cbgmres_solve on one request.  Arrival order is kept within each kind; small
+ * requests do not wait behind large ones.  The path depends on a request's
+ * shape only and neither path's arithmetic depends on the other requests, so
+ * a result is the same alone and in any mix.
  * ====================================================================== */
 typedef struct cb_server cb_server;
 
-/* Create a server on `device` with an HBM budget in bytes and `lanes`
- * concurrent solve lanes (streams).  NULL on failure (cb_last_error). */
+/* Create a server on `device` with an HBM budget in bytes, `lanes` solve
+ * lanes for large requests (1..64) and two batch lanes.  NULL on failure
+ * (cb_last_error). */
 cb_server* cb_server_create(size_t hbm_budget_bytes, int device, int lanes);
 
 /* Bytes a request of this shape is charged against the budget. */

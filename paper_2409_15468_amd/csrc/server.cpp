@@ -1,17 +1,22 @@
 // Continuous-batching solve server on one GPU.
 //
-// Requests enter a FIFO queue.  A request is admitted when its device
-// footprint (basis columns, CSR arrays, work vectors, reduction partials) fits
-// in what is left of the HBM budget; admitted requests run concurrently on a
-// pool of lanes, each lane a host worker thread with its own HIP stream, so
-// solves overlap on the device.  A lane that finds small requests at the head
-// of the queue takes all of them that fit (up to kMaxBatch) and solves them in
-// ONE persistent launch of the one-workgroup batched solver; a large request
-// gets a lane to itself and the multi-workgroup solver.  When a solve ends its
-// memory is returned to the budget and the next queued requests are admitted,
-// while the other lanes keep running.  Which path a request takes depends on
-// its own shape only, and neither path's arithmetic depends on what runs
-// beside it, so a result does not depend on the mix it ran in.
+// Requests enter a queue.  A request is admitted when its device footprint
+// (basis columns, CSR arrays, work vectors, reduction partials) fits in what
+// is left of the HBM budget.  Two kinds of lanes (host worker threads, each
+// with its own HIP stream) take admitted requests, so solves overlap on the
+// device:
+//  * solve lanes take large requests in arrival order, one at a time, and run
+//    the multi-workgroup solver on them;
+//  * batch lanes take every small request waiting (in arrival order, up to
+//    kMaxBatch, as far as the budget allows) and solve them in ONE persistent
+//    launch of the one-workgroup batched solver; small requests that arrive
+//    meanwhile are picked up by the next free batch lane.
+// Small requests never wait behind large ones for a lane (they use a few CUs
+// each).  When a solve ends its memory is returned to the budget and waiting
+// requests are admitted while the other lanes keep running.  Which path a
+// request takes depends on its own shape only, and neither path's arithmetic
+// depends on what runs beside it, so a result does not depend on the mix it
+// ran in.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -67,6 +72,7 @@ namespace cb {
 // Requests up to this size go to the batched one-workgroup solver.
 constexpr int32_t kSmallN = 16384;
 constexpr int kMaxBatch = 512;
+constexpr int kBatchLanes = 2;
 
 static bool is_small(int32_t n, int32_t m) { return n <= kSmallN && m <= kBatchMaxRestart; }
 
@@ -183,7 +189,33 @@ static int run_batch(std::vector<std::shared_ptr<Request>>& rs, hipStream_t s) {
     return st;
 }
 
-static void worker_main(cb_server* S) {
+// Under the lock: the requests a lane of this kind may take now.
+static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_lane) {
+    std::vector<std::shared_ptr<Request>> take;
+    int64_t charged = S->charged;
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+        const bool small = is_small((*it)->n, (*it)->m);
+        if (small != batch_lane) {
+            ++it;
+            continue;
+        }
+        // arrival order within the kind: stop at the first that does not fit
+        if (charged + (*it)->bytes > (int64_t)S->budget) break;
+        charged += (*it)->bytes;
+        take.push_back(*it);
+        it = S->queue.erase(it);
+        if ((int)take.size() >= (batch_lane ? kMaxBatch : 1)) break;
+    }
+    return take;
+}
+
+static bool has_kind(const cb_server* S, bool batch_lane) {
+    for (const auto& r : S->queue)
+        if (is_small(r->n, r->m) == batch_lane) return true;
+    return false;
+}
+
+static void worker_main(cb_server* S, bool batch_lane) {
     (void)hipSetDevice(S->device);
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
@@ -191,31 +223,22 @@ static void worker_main(cb_server* S) {
         std::vector<std::shared_ptr<Request>> take;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // FIFO admission: the head of the queue runs once it fits
-            S->cv.wait(lk, [&] {
-                return S->stopping ||
-                       (!S->queue.empty() && S->charged + S->queue.front()->bytes <= (int64_t)S->budget);
-            });
-            if (S->queue.empty()) {
-                if (S->stopping) break;
-                continue;
+            for (;;) {
+                take = take_work(S, batch_lane);
+                if (!take.empty()) break;
+                if (S->stopping && !has_kind(S, batch_lane)) break;
+                S->cv.wait(lk);
             }
-            if (S->charged + S->queue.front()->bytes > (int64_t)S->budget) continue;
-            // the head, and with a small head every small request behind it that fits
-            const bool small = is_small(S->queue.front()->n, S->queue.front()->m);
-            while (!S->queue.empty() && (int)take.size() < (small ? kMaxBatch : 1)) {
-                auto& q = S->queue.front();
-                if (is_small(q->n, q->m) != small || S->charged + q->bytes > (int64_t)S->budget) break;
-                S->charged += q->bytes;
-                q->t_start = S->now();
-                take.push_back(q);
-                S->queue.pop_front();
+            if (take.empty()) break;
+            const double t = S->now();
+            for (auto& r : take) {
+                S->charged += r->bytes;
+                r->t_start = t;
             }
             S->running += (int)take.size();
         }
-        int st = CB_OK;
-        if (take.size() == 1 && !is_small(take[0]->n, take[0]->m)) {
-            st = run_request(*take[0], s);
+        if (!batch_lane) {
+            int st = run_request(*take[0], s);
             if (st == CB_PENDING) st = CB_ERR_HIP;
             take[0]->result.status = st;
         } else {
@@ -266,7 +289,8 @@ cb_server* cb_server_create(size_t hbm_budget_bytes, int device, int lanes) {
     S->budget = hbm_budget_bytes;
     S->device = device;
     S->t0 = std::chrono::steady_clock::now();
-    for (int i = 0; i < lanes; ++i) S->workers.emplace_back(worker_main, S);
+    for (int i = 0; i < lanes; ++i) S->workers.emplace_back(worker_main, S, false);
+    for (int i = 0; i < kBatchLanes; ++i) S->workers.emplace_back(worker_main, S, true);
     return S;
 }
 

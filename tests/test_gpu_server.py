@@ -5,7 +5,8 @@ independence from the mix.
   server or among others (same kernels, same reduction order per request),
   and meets its own tolerance.
 * A budget that fits one request at a time forces queueing; every request
-  still completes, in FIFO admission order.
+  still completes, admitted in arrival order within its kind (small requests
+  batched, large ones one per lane).
 * A request larger than the whole budget is rejected with CB_ERR_OVER_BUDGET.
 """
 import time
@@ -76,9 +77,10 @@ def test_budget_forces_queueing_and_rejects_oversize():
              for r, s in items]
     for t0, _, _ in spans:  # at every admission the running set fits the budget
         assert sum(b for s0, e0, b in spans if s0 <= t0 < e0) <= need
-    # FIFO admission: requests start in submission order
-    starts = [out[r.rid][2][1] for r, _ in items]
-    assert starts == sorted(starts)
+    # admission in arrival order within each kind (batched small / large)
+    for small in (True, False):
+        starts = [out[r.rid][2][1] for r, s in items if (s.A.n <= 16384 and r.m <= 104) == small]
+        assert starts == sorted(starts)
     big = synth.sweep_3d(N=60, seed=1)
     assert cb.Server.request_bytes(big.A.n, big.A.nnz, 100, "float64") > need
     with pytest.raises(cb.CbError) as ei:
