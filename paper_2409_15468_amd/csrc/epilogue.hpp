@@ -13,8 +13,9 @@
 // groups still stream, so the final workgroup adds only a few values per
 // column.  Partials are written with device-scope (agent) relaxed atomic
 // stores, which are coherent across the XCDs' L2 caches, and each thread waits
-// for its stores to complete before a ticket is drawn; a workgroup that goes
-// on to read other workgroups' partials first acquires at device scope.
+// for its stores to complete before a ticket is drawn; the workgroups that go
+// on to read other workgroups' partials read them with device-scope atomic
+// loads, so no cache-wide invalidation is needed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -100,7 +101,7 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ partials
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int kk = k + u * tpc;
-                q[u] = kk < M ? p[(int64_t)kk * stride] : 0.0;
+                q[u] = kk < M ? ld_ctl(p + (int64_t)kk * stride) : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) s += q[u];
@@ -186,7 +187,7 @@ constexpr int kMaxTicketGroups = kCounterBytes / 128 - 1;
 
 __device__ __forceinline__ bool draw_last(unsigned* c, unsigned count) {
     const bool last = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == count - 1;
-    if (last) *c = 0u;
+    if (last) __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next launch
     return last;
 }
 
@@ -207,7 +208,6 @@ __device__ __forceinline__ bool reduce_tickets(const Epi& e, double* partials, d
         flag = draw_last(e.counter + kCounterLine * (1 + blockIdx.y * ng + q), (unsigned)gsize);
     __syncthreads();
     if (!flag) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // the group's sums, over the partial of its first workgroup
     for (int a = c0; a < c1; a += 256) {
         const int nc = min(256, c1 - a);
@@ -219,9 +219,7 @@ __device__ __forceinline__ bool reduce_tickets(const Epi& e, double* partials, d
     __syncthreads();
     if (threadIdx.x == 0) flag = draw_last(e.counter, gridDim.y * (unsigned)ng);
     __syncthreads();
-    if (!flag) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return true;
+    return flag != 0;
 }
 
 // In the last workgroup: lds[i] = the full sum of column a + i, i < nc.
@@ -233,7 +231,7 @@ __device__ __forceinline__ void reduce_final(const Epi& e, const double* partial
 // sum of p[0 .. G) in a fixed order, valid in thread 0
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int G) {
     double t = 0.0;
-    for (int k = threadIdx.x; k < G; k += blockDim.x) t += p[k];
+    for (int k = threadIdx.x; k < G; k += blockDim.x) t += ld_ctl(p + k);
     return block_sum<256>(t);
 }
 
