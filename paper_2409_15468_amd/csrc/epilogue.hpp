@@ -228,10 +228,18 @@ __device__ __forceinline__ void reduce_final(const Epi& e, const double* partial
     reduce_range(partials, e.G, 0, ng, kTicketGroup, a, nc, lds);
 }
 
-// sum of p[0 .. G) in a fixed order, valid in thread 0
+// sum of p[0 .. G) in a fixed order, valid in thread 0 (blockDim.x == 256):
+// thread t adds p[t], p[t + 256], ... in order, eight loads in flight at a
+// time, then the threads are summed with block_sum.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int G) {
     double t = 0.0;
-    for (int k = threadIdx.x; k < G; k += blockDim.x) t += ld_ctl(p + k);
+    for (int k = threadIdx.x; k < G; k += 8 * 256) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = k + u * 256 < G ? ld_ctl(p + k + u * 256) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t += q[u];
+    }
     return block_sum<256>(t);
 }
 
