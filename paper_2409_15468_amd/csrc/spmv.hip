@@ -1,13 +1,15 @@
 // CSR sparse matrix-vector product in FP64 (Fig. 1 steps 1 and 3) with the
 // squared norm of the result fused in (step 4).
 //
-// A group of LPR lanes works on one row: lane i of the group accumulates the
-// row's entries i, i+LPR, ... with FMA in CSR order, then the group sums with a
-// fixed shuffle tree.  LPR is the power of two nearest to half the average row
-// length (4 for the 5- and 7-point stencils), so most lanes own one or two
-// nonzeros and the row's column indices are read as one coalesced run.  At
-// most kSpmvGroups workgroups loop over the blocks of 256/LPR rows; the
-// row-to-workgroup map depends on the matrix only, keeping the norm's
+// Short rows (the 5- and 7-point stencils): a wave stages the products of 64
+// rows' nonzeros in LDS from coalesced loads and each lane adds its row's
+// products in CSR order (spmv_rows_staged).  Longer rows: a group of LPR lanes
+// works on one row: lane i of the group accumulates the row's entries i,
+// i+LPR, ... with FMA in CSR order, then the group sums with a fixed shuffle
+// tree; LPR is the power of two nearest to half the average row length, so
+// most lanes own one or two nonzeros and a row's column indices are read as
+// one coalesced run.  At most kSpmvGroups workgroups loop over the row blocks;
+// the row-to-workgroup map depends on the matrix only, keeping the norm's
 // reduction order fixed.
 #include "cb_internal.hpp"
 #include "epilogue.hpp"
@@ -50,6 +52,58 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
     return nrm;
 }
 
+// Short rows (at most 8 nonzeros per row on average): a wave takes 64
+// consecutive rows; their nonzeros, a contiguous run of at most 512 entries,
+// are read as 8 coalesced loads per lane, multiplied by the gathered x (x[c] /
+// d when DIV) into LDS, and each lane then adds its row's products in CSR
+// order.  A run longer than 512 entries falls back to one lane per row.
+// With b != NULL the result is b - A x.  Returns this thread's share of
+// ||y||^2.
+constexpr int kStagedMax = 512;
+template <bool DIV>
+__device__ __forceinline__ double spmv_rows_staged(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ val, const double* __restrict__ xs,
+                                                   double d, const double* __restrict__ b, double* __restrict__ y,
+                                                   double* prod) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwb = (n + 63) / 64;  // blocks of 64 rows
+    double nrm = 0.0;
+    for (int wb = blockIdx.x * 4 + wave; wb < nwb; wb += gridDim.x * 4) {
+        const int r = wb * 64 + lane;
+        const int rr = r < n ? r : n;
+        const int my0 = rp[rr], my1 = r < n ? rp[r + 1] : my0;
+        const int k0 = __builtin_amdgcn_readfirstlane(my0);
+        const int k1 = __builtin_amdgcn_readlane(my1, 63);
+        double s = 0.0;
+        if (k1 - k0 <= kStagedMax) {
+#pragma unroll
+            for (int c = 0; c < kStagedMax / 64; ++c) {
+                const int k = k0 + c * 64 + lane;
+                double pv = 0.0;
+                if (k < k1) {
+                    const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
+                    pv = val[k] * xv;
+                }
+                prod[c * 64 + lane] = pv;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int k = my0; k < my1; ++k) s += prod[k - k0];
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            for (int k = my0; k < my1; ++k) {
+                const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
+                s = fma(val[k], xv, s);
+            }
+        }
+        if (r < n) {
+            if (b) s = b[r] - s;
+            y[r] = s;
+            nrm = fma(s, s, nrm);
+        }
+    }
+    return nrm;
+}
+
 // Fig. 1 steps 13-14 of the previous step fused with steps 3-4 of this one:
 // column col of the basis := Q(w / d) (IEEE division per entry, as k_store),
 // and y = A (w / d) with the quotients formed again where the SpMV reads them
@@ -78,7 +132,9 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
     }
     if (bad) atomicOr(flag, 1);
     double nrm;
+    __shared__ double prod[4][kStagedMax];
     switch (lpr) {
+    case 0: nrm = spmv_rows_staged<true>(n, rp, ci, val, w, d, nullptr, y, prod[threadIdx.x >> 6]); break;
     case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, y); break;
     case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, y); break;
     case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, y); break;
@@ -89,6 +145,23 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
     }
     const double t = block_sum<256>(nrm);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_spmv_staged(int n, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ y,
+                                                     double* __restrict__ partials, int mode,
+                                                     const int* __restrict__ guard) {
+    if (guard && ld_ctl(guard) == 0) return;
+    __shared__ double prod[4][kStagedMax];
+    const double nrm = spmv_rows_staged<false>(n, rp, ci, val, x, 1.0, mode ? b : nullptr, y,
+                                               prod[threadIdx.x >> 6]);
+    if (partials) {
+        const double t = block_sum<256>(nrm);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
 }
 
 template <int LPR>
@@ -127,7 +200,11 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     }
 }
 
+// 0 selects the staged short-row scheme (at most 8 nonzeros per row on
+// average), else the lanes per row: the power of two nearest to half the
+// average row length.
 int spmv_lanes_per_row(int32_t n, int32_t nnz) {
+    if ((int64_t)nnz <= 8 * (int64_t)n) return 0;
     double avg = n > 0 ? (double)nnz / (double)n : 1.0;
     int lpr = 1;
     while (lpr < 64 && 2.0 * lpr <= avg) lpr *= 2;
@@ -137,7 +214,8 @@ int spmv_lanes_per_row(int32_t n, int32_t nnz) {
 // Workgroups of the SpMV: one per block of rows up to kSpmvGroups, which then
 // loop over blocks; few partial sums keep their consumer's reduction short.
 int spmv_groups(int32_t n, int32_t nnz) {
-    const int rpw = 256 / spmv_lanes_per_row(n, nnz);
+    const int lpr = spmv_lanes_per_row(n, nnz);
+    const int rpw = lpr ? 256 / lpr : 256;
     const int64_t blocks = ((int64_t)n + rpw - 1) / rpw;
     return (int)(blocks < kSpmvGroups ? blocks : kSpmvGroups);
 }
@@ -151,6 +229,9 @@ void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, d
         k_spmv<L><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard); \
         break;
     switch (lpr) {
+    case 0:
+        k_spmv_staged<<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard);
+        break;
         CB_SPMV_CASE(1)
         CB_SPMV_CASE(2)
         CB_SPMV_CASE(4)

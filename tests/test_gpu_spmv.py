@@ -1,5 +1,6 @@
 """GPU parity of the CSR SpMV and residual kernels against the oracle, for
-row lengths that select every lanes-per-row width (empty rows, stencils,
+row lengths that select every scheme (the staged short-row scheme with its
+long-block fallback, and the lanes-per-row widths: empty rows, stencils,
 27-entry banded rows, long rows), plus the fused squared norm."""
 import numpy as np
 import pytest
@@ -25,6 +26,21 @@ def random_rows(n, avg, seed):
     return synth.CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
 
 
+def skewed(n, seed):
+    """Mostly 2-entry rows with a few 600-entry rows: short on average (the
+    staged scheme) but with 64-row blocks longer than its 512-entry stage,
+    which take the one-lane-per-row path."""
+    rng = np.random.default_rng(seed)
+    lens = np.full(n, 2)
+    lens[rng.choice(n, 8, replace=False)] = 600
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, n, rows.size)
+    M = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(n, n))
+    M.sum_duplicates()
+    M.sort_indices()
+    return synth.CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data)
+
+
 MATRICES = {
     "cd2d": lambda: synth.convection_diffusion(40, 2, (20.0, 0.0)),
     "cd3d": lambda: synth.convection_diffusion(17, 3, (10.0, 5.0, 2.0)),
@@ -32,6 +48,7 @@ MATRICES = {
     "sparse1": lambda: random_rows(2000, 1.0, 1),
     "long64": lambda: random_rows(700, 140.0, 2),
     "mid20": lambda: random_rows(1500, 20.0, 3),
+    "skewed": lambda: skewed(3001, 4),
 }
 
 
