@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--micro-reps", type=int, default=5)
     ap.add_argument("--micro-formats", default="frsz2_32,frsz2_21,frsz2_16,float32,float64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--all-formats", action="store_true",
+                    help="also time the sweep solve with the float32, float16, frsz2_16 and frsz2_21 bases")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="microbench only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -387,6 +389,19 @@ def main():
                         "reorths": r_d["reorths"], "rel_residual": r_d["rel_residual"]},
             "speedup_frsz2_32_vs_float64": t_d / t_z,
         }
+        if args.all_formats:
+            for fmt in ("float32", "float16", "frsz2_16", "frsz2_21"):
+                log(f"bench: {fmt} solves")
+                t_f, r_f = timed_solves(cb, torch, A, b, x, fmt, m, tol, args.steps, args.warmup, ws)
+                xf = x.cpu().numpy()
+                rec["solve"][fmt] = {
+                    "seconds": t_f, "iterations": r_f["iterations"], "cycles": r_f["restarts"],
+                    "reorths": r_f["reorths"], "converged": bool(r_f["converged"]),
+                    "rel_residual": float(np.linalg.norm(s.b - s.A.scipy() @ xf) / np.linalg.norm(s.b)),
+                    "err_vs_xstar": float(np.linalg.norm(xf - s.x_star) / np.linalg.norm(s.x_star)),
+                    "err_vs_fp64_basis": float(np.linalg.norm(xf - x64) / np.linalg.norm(x64)),
+                    "speedup_vs_float64": t_d / t_f}
+                log(f"bench: {fmt} {t_f * 1e3:.1f} ms, {r_f['iterations']} iters")
     del ws
     torch.cuda.empty_cache()
 
