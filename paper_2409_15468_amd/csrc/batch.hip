@@ -281,10 +281,22 @@ __device__ void batch_solve(const BatchItem& it, const BatchOpts& o, cb_result* 
                     double* h = S.h;
                     h[j + 1] = hn;
                     double carry = h[0];
-                    for (int i = 0; i < j; ++i) {
-                        const double b1 = h[i + 1], c = S.cs[i], s = S.sn[i];
-                        h[i] = c * carry + s * b1;
-                        carry = -s * carry + c * b1;
+                    for (int i0 = 0; i0 < j; i0 += 16) {  // LDS reads of 16 rotations ahead
+                        double b1[16], c[16], s[16];
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            const int i = min(i0 + k, j - 1);
+                            b1[k] = h[i + 1];
+                            c[k] = S.cs[i];
+                            s[k] = S.sn[i];
+                        }
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) {
+                            if (i0 + k < j) {
+                                h[i0 + k] = c[k] * carry + s[k] * b1[k];
+                                carry = -s[k] * carry + c[k] * b1[k];
+                            }
+                        }
                     }
                     h[j] = carry;
                     const double rho = sqrt(h[j] * h[j] + hn * hn);

@@ -146,11 +146,28 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
     if (threadIdx.x == 0) {
         if (hn == 0.0) breakdown = 1;
         lh[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            const double a = lh[i], b = lh[i + 1];
-            lh[i] = lc[i] * a + ls[i] * b;
-            lh[i + 1] = -ls[i] * a + lc[i] * b;
+        // the earlier rotations in order; the entry carried from rotation i to
+        // i+1 stays in a register, and the LDS reads of each chunk of 16
+        // rotations are issued together ahead of the arithmetic
+        double carry = lh[0];
+        for (int i0 = 0; i0 < j; i0 += 16) {
+            double b[16], c[16], sn[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int i = min(i0 + k, j - 1);
+                b[k] = lh[i + 1];
+                c[k] = lc[i];
+                sn[k] = ls[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (i0 + k < j) {
+                    lh[i0 + k] = c[k] * carry + sn[k] * b[k];
+                    carry = -sn[k] * carry + c[k] * b[k];
+                }
+            }
         }
+        lh[j] = carry;
         const double rho = sqrt(lh[j] * lh[j] + hn * hn);
         const double c = lh[j] / rho, sn = hn / rho;
         e.cs[j] = c;
