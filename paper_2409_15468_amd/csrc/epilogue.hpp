@@ -119,11 +119,37 @@ __device__ __forceinline__ void reduce_range(const double* __restrict__ partials
     __syncthreads();
 }
 
+// The control-block fields the last workgroup's thread 0 needs, read once
+// with control loads issued together (one memory round trip instead of one
+// per field), and g_j.
+struct Snap {
+    double eta, omega, omega_pre, basis_bytes, tol_abs, gj;
+    int literal, reorths, iters, max_iters, breakdowns;
+};
+__device__ __forceinline__ Snap snapshot(const Epi& e) {
+    const State* st = e.st;
+    Snap z;
+    z.eta = ld_ctl(&st->eta);
+    z.omega = ld_ctl(&st->omega);
+    z.omega_pre = ld_ctl(&st->omega_pre);
+    z.basis_bytes = ld_ctl(&st->basis_bytes);
+    z.tol_abs = ld_ctl(&st->tol_abs);
+    z.literal = ld_ctl(&st->literal);
+    z.reorths = ld_ctl(&st->reorths);
+    z.iters = ld_ctl(&st->iters);
+    z.max_iters = ld_ctl(&st->max_iters);
+    z.breakdowns = ld_ctl(&st->breakdowns);
+    z.gj = ld_ctl(&e.g[e.j]);
+    return z;
+}
+
 // Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
 // Givens rotations, implicit residual, end-of-cycle decision.  Called by all
-// threads of one workgroup; H column j, cs and sn are staged in LDS.
-__device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, double* lds) {
-    volatile State& s = *e.st;
+// threads of one workgroup; H column j, cs and sn are staged in LDS; z is
+// valid in thread 0.  Results go to memory with plain stores (read by later
+// kernels on the stream and by the host after it synchronises).
+__device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, const Snap& z, double* lds) {
+    State& s = *e.st;
     const int j = e.j;
     double* h = e.H + (int64_t)j * (e.m + 1);
     double* lh = lds;                // j + 2 entries
@@ -174,16 +200,18 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
         e.sn[j] = sn;
         lh[j] = rho;
         lh[j + 1] = 0.0;
-        const double gj = ld_ctl(&e.g[j]);
-        e.g[j + 1] = -sn * gj;
-        e.g[j] = c * gj;
-        s.iters += 1;
+        const double g1 = -sn * z.gj;
+        e.g[j + 1] = g1;
+        e.g[j] = c * z.gj;
+        const int iters = z.iters + 1;
+        const double gabs = fabs(g1);
+        s.iters = iters;
         s.steps = j + 1;
-        s.gabs = fabs(e.g[j + 1]);
-        e.hist[j] = s.gabs;
-        if (s.gabs <= s.tol_abs || breakdown || s.iters >= s.max_iters || j + 1 == e.m) {
+        s.gabs = gabs;
+        e.hist[j] = gabs;
+        if (gabs <= z.tol_abs || breakdown || iters >= z.max_iters || j + 1 == e.m) {
             s.active = 0;
-            s.breakdowns += breakdown;
+            s.breakdowns = z.breakdowns + breakdown;
         }
     }
     __syncthreads();
@@ -289,34 +317,38 @@ __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double*
     if (e.mode == EPI_STEP_CHECK) om2 = sum_partials(e.extra, e.extra_G);
     __shared__ int do_finish, bd;
     __shared__ double hn_s;
+    Snap z;
     if (threadIdx.x == 0) {
-        volatile State& s = *e.st;
+        z = snapshot(e);
+        State& s = *e.st;
         do_finish = 0;
         bd = 0;
+        const double hn = sqrt(t);
         s.hn2 = t;
-        s.hn = sqrt(t);
-        hn_s = s.hn;
+        s.hn = hn;
+        hn_s = hn;
         if (e.mode == EPI_STEP_CHECK) {
+            const double omega = sqrt(om2);
             s.om2 = om2;
-            s.omega = sqrt(om2);
-            s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
-            if (s.hn < s.eta * s.omega) {
+            s.omega = omega;
+            s.basis_bytes = z.basis_bytes + 2.0 * (e.j + 1) * e.col_bytes;
+            if (hn < z.eta * omega) {
                 s.reorth = 1;  // steps 7-11 follow
-                s.omega_pre = s.hn;
+                s.omega_pre = hn;
             } else {
                 s.reorth = 0;
                 do_finish = 1;
             }
         } else {  // EPI_REORTH_FINISH
-            s.reorths += 1;
-            s.basis_bytes += 2.0 * (e.j + 1) * e.col_bytes;
-            bd = s.literal ? (s.hn < s.eta * s.omega) : (s.hn < s.eta * s.omega_pre);
+            s.reorths = z.reorths + 1;
+            s.basis_bytes = z.basis_bytes + 2.0 * (e.j + 1) * e.col_bytes;
+            bd = z.literal ? (hn < z.eta * z.omega) : (hn < z.eta * z.omega_pre);
             s.reorth = 0;
             do_finish = 1;
         }
     }
     __syncthreads();
-    if (do_finish) finish_step(e, bd, hn_s, lds);
+    if (do_finish) finish_step(e, bd, hn_s, z, lds);
 }
 
 }  // namespace dev
