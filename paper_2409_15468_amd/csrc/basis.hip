@@ -151,6 +151,83 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
     }
 }
 
+// The first Gram-Schmidt update fused with the second projection (Fig. 1 steps
+// 5b-6 and 8): w -= sum_{c<j} h[c] D(v_c) over the workgroup's row groups,
+// then u_c = <D(v_c), w> for c < j on the updated rows, which are still in
+// registers.  partials[c * G + g] holds the workgroup's u_c for c < j and its
+// ||w||^2 at c = j; the epilogue (FUSED_CHECK) keeps u only if step 7 asks for
+// the second pass.  Sums are formed in the same orders as k_subtract (norm)
+// and k_project with one column chunk (u).
+template <int FMT, int U>
+__global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int j,
+                                                               const double* __restrict__ h,
+                                                               double* __restrict__ w,
+                                                               double* __restrict__ partials, int stream,
+                                                               const int* __restrict__ guard, Epi e) {
+    if (guard && ld_ctl(guard) == 0) return;
+    __shared__ double elds[kEpiLds];
+    __shared__ double hc[kMaxRestart + 1];
+    __shared__ double red[kThreads / 64][kMaxRestart + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = gridDim.x;
+    const int ngroups = row_groups_dev(V.np);
+    for (int i = tid; i < j; i += kThreads) hc[i] = ld_ctl(&h[i]);
+    for (int i = lane; i < j; i += 64) red[wave][i] = 0.0;
+    __syncthreads();
+    double nrm = 0.0;
+    for (int rg = blockIdx.x; rg < ngroups; rg += G) {
+        const int tile0 = rg * kRowsPerWG + wave * kTile;
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        const bool full = tile0 + kTile <= V.np;
+        if (stream) {
+            if (full) subtract_tile<FMT, U, kFull | kStream>(V, j, hc, tile0, lane, acc);
+            else subtract_tile<FMT, U, kStream>(V, j, hc, tile0, lane, acc);
+        } else {
+            if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
+            else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
+        }
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            wv[q] = wv[q] - acc[q];
+            t = fma(wv[q], wv[q], t);  // rows >= n hold 0
+        }
+        nrm += t;
+        store_rows<FMT>(w, tile0, lane, V.n, wv);
+        if constexpr (FMT == CB_F64) {  // 4 column tiles at a time: fewer registers, same sums
+            if (stream) {
+                if (full) project_tile_narrow<FMT, kFull | kStream>(V, 0, j, tile0, lane, wv, red[wave]);
+                else project_tile_narrow<FMT, kStream>(V, 0, j, tile0, lane, wv, red[wave]);
+            } else {
+                if (full) project_tile_narrow<FMT, kFull>(V, 0, j, tile0, lane, wv, red[wave]);
+                else project_tile_narrow<FMT, 0>(V, 0, j, tile0, lane, wv, red[wave]);
+            }
+        } else {
+            if (stream) {
+                if (full) project_tile<FMT, kFull | kStream>(V, 0, j, tile0, lane, wv, red[wave]);
+                else project_tile<FMT, kStream>(V, 0, j, tile0, lane, wv, red[wave]);
+            } else {
+                if (full) project_tile<FMT, kFull>(V, 0, j, tile0, lane, wv, red[wave]);
+                else project_tile<FMT, 0>(V, 0, j, tile0, lane, wv, red[wave]);
+            }
+        }
+    }
+    const double wn = wave_sum(nrm);
+    if (lane == 0) red[wave][j] = wn;
+    __syncthreads();
+    for (int i = tid; i <= j; i += kThreads) {
+        double s = red[0][i];
+#pragma unroll
+        for (int k = 1; k < kThreads / 64; ++k) s += red[k][i];
+        store_partial(partials + (int64_t)i * G + blockIdx.x, s);
+    }
+    epilogue(e, partials, elds);
+}
+
 // ----------------------------------------------------------------- stage 2
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partials, int G,
                                                 double* __restrict__ out, int op,
@@ -254,6 +331,19 @@ void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const d
     const int stream = streams_basis(b, j);
     CB_DISPATCH(fmt, (k_subtract<F, 4><<<grid, kThreads, 0, s>>>(b, j, jdev, h, w, partials, sign, stream,
                                                                 guard, ee)));
+}
+
+void launch_subtract_project(int fmt, const cb_basis& V, int j, const double* h, double* w, double* partials,
+                             const int* guard, const Epi& e, hipStream_t s) {
+    BasisView b = view_of(V);
+    const int G = project_groups(V.n);
+    dim3 grid((unsigned)G);
+    Epi ee = e;
+    ee.G = G;
+    ee.ncols = j + 1;  // u_0 .. u_{j-1} and the norm
+    ee.cw = j + 1;
+    const int stream = streams_basis(b, j);
+    CB_DISPATCH(fmt, (k_subtract_project<F, 4><<<grid, kThreads, 0, s>>>(b, j, h, w, partials, stream, guard, ee)));
 }
 
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op, const int* guard,

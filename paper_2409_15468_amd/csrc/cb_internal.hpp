@@ -95,6 +95,10 @@ void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* 
 void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const double* h,
                      double* w, double* partials, const int* guard, int accumulate_sign,
                      const Epi& e, hipStream_t s);
+// w -= V h (h device, j coefficients), then partials of u = V^T w (c < j) and
+// ||w||^2 (c = j), and the epilogue e (FUSED_CHECK).
+void launch_subtract_project(int fmt, const cb_basis& V, int j, const double* h, double* w, double* partials,
+                             const int* guard, const Epi& e, hipStream_t s);
 void launch_zero_counter(unsigned* counter, hipStream_t s);
 // Stage 2: out[c] (op 0: =, op 1: +=) = sum_g partials[c * G + g], c < ncols.
 void launch_reduce(const double* partials, int G, int ncols, double* out, int op,

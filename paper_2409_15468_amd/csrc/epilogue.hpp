@@ -54,6 +54,9 @@ enum EpiMode : int {
     EPI_STEP_CHECK = 1,     // first Gram-Schmidt pass done: norm -> step 7 test
     EPI_REORTH_PROJECT = 2, // u = sum; h += u
     EPI_REORTH_FINISH = 3,  // second pass done: norm -> breakdown test, Givens
+    EPI_FUSED_CHECK = 4,    // first update fused with the second projection:
+                            // sums u_0..u_{ncols-2} and ||w||^2 (last column) ->
+                            // step 7 test; u kept (h += u) only if it asks for it
 };
 
 struct Epi {
@@ -75,6 +78,7 @@ struct Epi {
     int j;                 // Arnoldi step (0-based): column j of H
     int m;
     double col_bytes;
+    int fused;             // this cycle runs the first update fused with the second projection
 };
 
 namespace dev {
@@ -288,10 +292,80 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
     return block_sum<256>(t);
 }
 
+// Fig. 1 steps 6-12 once ||w||^2 = t after a Gram-Schmidt pass is known
+// (the STEP_CHECK / FUSED_CHECK / REORTH_FINISH modes; last workgroup, all
+// threads): h_{j+1,j}, the step 7 test, the breakdown test, then the Givens
+// update of finish_step when the step is complete.  In FUSED_CHECK mode u
+// (e.out) is added to H column j when the second pass is needed, else dropped.
+__device__ __forceinline__ void step_logic(const Epi& e, double t, double* lds) {
+    // the SpMV's ||A v||^2 partials, when this step needs omega
+    double om2 = 0.0;
+    if (e.mode != EPI_REORTH_FINISH) om2 = sum_partials(e.extra, e.extra_G);
+    __shared__ int do_finish, bd, keep_u;
+    __shared__ double hn_s;
+    Snap z;
+    if (threadIdx.x == 0) {
+        z = snapshot(e);
+        State& s = *e.st;
+        do_finish = 0;
+        bd = 0;
+        keep_u = 0;
+        const double hn = sqrt(t);
+        s.hn2 = t;
+        s.hn = hn;
+        hn_s = hn;
+        if (e.mode == EPI_STEP_CHECK || e.mode == EPI_FUSED_CHECK) {
+            const double omega = sqrt(om2);
+            const bool fused = e.mode == EPI_FUSED_CHECK;
+            s.om2 = om2;
+            s.omega = omega;
+            // the first projection and update (and the fused second projection)
+            s.basis_bytes = z.basis_bytes + (fused ? 3.0 : 2.0) * (e.j + 1) * e.col_bytes;
+            if (hn < z.eta * omega) {
+                s.reorth = 1;  // steps 7-11 follow
+                s.omega_pre = hn;
+                keep_u = fused;  // a fused launch has computed u already
+            } else {
+                s.reorth = 0;
+                do_finish = 1;
+            }
+        } else {  // EPI_REORTH_FINISH
+            s.reorths = z.reorths + 1;
+            // the second update, and the second projection if it ran apart
+            s.basis_bytes = z.basis_bytes + (e.fused ? 1.0 : 2.0) * (e.j + 1) * e.col_bytes;
+            bd = z.literal ? (hn < z.eta * z.omega) : (hn < z.eta * z.omega_pre);
+            s.reorth = 0;
+            do_finish = 1;
+        }
+    }
+    __syncthreads();
+    if (keep_u) {  // h_{1:j+1,j} += u
+        double* h = e.H + (int64_t)e.j * (e.m + 1);
+        for (int i = threadIdx.x; i < e.ncols - 1; i += blockDim.x) h[i] += e.out[i];
+        __syncthreads();
+    }
+    if (do_finish) finish_step(e, bd, hn_s, z, lds);
+}
+
 // Run by every workgroup of the launch after its partials are written
 // (all threads; blockDim.x == 256).
 __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double* lds) {
     if (!reduce_tickets(e, partials, lds)) return;
+    if (e.mode == EPI_FUSED_CHECK) {
+        // u_c (c < ncols - 1) into e.out, ||w||^2 from the last column
+        __shared__ double nn;
+        for (int c0 = 0; c0 < e.ncols; c0 += 256) {
+            const int nc = min(256, e.ncols - c0);
+            reduce_final(e, partials, c0, nc, lds);
+            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+                if (c0 + i < e.ncols - 1) e.out[c0 + i] = lds[i];
+                else nn = lds[i];
+            }
+            __syncthreads();
+        }
+        step_logic(e, nn, lds);
+        return;
+    }
     if ((e.mode == EPI_STORE && e.ncols > 1) || e.mode == EPI_REORTH_PROJECT) {
         for (int c0 = 0; c0 < e.ncols; c0 += 256) {
             const int nc = min(256, e.ncols - c0);
@@ -312,43 +386,7 @@ __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double*
         if (threadIdx.x == 0) e.out[0] = t;
         return;
     }
-    // the SpMV's ||A v||^2 partials, when this step needs omega
-    double om2 = 0.0;
-    if (e.mode == EPI_STEP_CHECK) om2 = sum_partials(e.extra, e.extra_G);
-    __shared__ int do_finish, bd;
-    __shared__ double hn_s;
-    Snap z;
-    if (threadIdx.x == 0) {
-        z = snapshot(e);
-        State& s = *e.st;
-        do_finish = 0;
-        bd = 0;
-        const double hn = sqrt(t);
-        s.hn2 = t;
-        s.hn = hn;
-        hn_s = hn;
-        if (e.mode == EPI_STEP_CHECK) {
-            const double omega = sqrt(om2);
-            s.om2 = om2;
-            s.omega = omega;
-            s.basis_bytes = z.basis_bytes + 2.0 * (e.j + 1) * e.col_bytes;
-            if (hn < z.eta * omega) {
-                s.reorth = 1;  // steps 7-11 follow
-                s.omega_pre = hn;
-            } else {
-                s.reorth = 0;
-                do_finish = 1;
-            }
-        } else {  // EPI_REORTH_FINISH
-            s.reorths = z.reorths + 1;
-            s.basis_bytes = z.basis_bytes + 2.0 * (e.j + 1) * e.col_bytes;
-            bd = z.literal ? (hn < z.eta * z.omega) : (hn < z.eta * z.omega_pre);
-            s.reorth = 0;
-            do_finish = 1;
-        }
-    }
-    __syncthreads();
-    if (do_finish) finish_step(e, bd, hn_s, z, lds);
+    step_logic(e, t, lds);
 }
 
 }  // namespace dev

@@ -5,13 +5,17 @@
 // 7), breakdown (step 12), the Givens rotations and the implicit residual
 // (steps 16-17), the end of a cycle -- is taken on the GPU, by the last
 // workgroup of the kernel whose reduction it needs (epilogue.hpp), and written
-// to a control block in device memory.  A step is five launches: the
-// normalise-and-store of the step's basis vector fused with the SpMV on it
-// (+ its norm), projection (+ h), update (+ norm and step 7 test), and the
-// second projection and update when step 7 asks for them (+ breakdown test
-// and Givens rotation); the SpMV's norm is summed by the first update's last
-// workgroup.  w alternates between two buffers, since the fused kernel reads
-// the previous w at other rows while it writes the new one.  The host
+// to a control block in device memory.  A step is: the normalise-and-store of
+// the step's basis vector fused with the SpMV on it (+ its norm), projection
+// (+ h), update (+ norm and step 7 test), and the second projection and update
+// when step 7 asks for them (+ breakdown test and Givens rotation); the SpMV's
+// norm is summed by the first update's last workgroup.  In a cycle that
+// follows one where most steps needed the second pass, the first update runs
+// fused with the second projection (its rows are projected again while they
+// are still in registers), saving a launch per step; the projection is then
+// formed speculatively and dropped when step 7 does not ask for it.  w
+// alternates between two buffers, since the fused store+SpMV kernel reads the
+// previous w at other rows while it writes the new one.  The host
 // enqueues a whole cycle of m steps without waiting; kernels of steps after
 // the cycle has ended read the control block and return at once.  The host
 // waits once per cycle, after the explicit residual of the restart (step 1 /
@@ -55,7 +59,7 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     L.exps = take(exponent_words(fmt, n) * 4 * (m + 1));
     // partial sums: the basis kernels' groups times columns, one per row group
     // of k_sumsq, or one per SpMV workgroup (the IR residual)
-    int64_t np_ = (int64_t)project_groups(n) * (m + 1);
+    int64_t np_ = (int64_t)project_groups(n) * (m + 2);
     if (np_ < row_groups(n)) np_ = row_groups(n);
     if (np_ < kSpmvGroups) np_ = kSpmvGroups;
     L.part = take(8 * np_);
@@ -133,6 +137,7 @@ __global__ __launch_bounds__(256) void k_cycle_begin(State* st, const int32_t* f
             s.cycles += 1;
             go = 1;
         }
+
     }
     __syncthreads();
     if (go)
@@ -269,6 +274,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     } else {
         int cycles = 0;
         bool capped = false;
+        bool fused = true;
+        int prev_iters = 0, prev_reorths = 0;
         for (;;) {
             // restart: explicit residual into w, beta, stop test
             launch_spmv(A, x, b, w, part_s, 1, nullptr, s);
@@ -281,6 +288,20 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                     history_host[recorded++] = hh[k] / hs->nb;
             }
             if (hs->stop) break;
+            // Fuse the first update with the second projection in this cycle
+            // when the last cycle re-orthogonalised at least half its steps
+            // (the first cycle assumes so); the decision depends on the
+            // solve's own history only.  A float64 basis keeps the separate
+            // launches: with 16-byte-per-lane float64 tiles the fused kernel
+            // holds half as many loads in flight and measured no faster.
+            if (cycles > 0) {
+                const int steps_done = hs->iters - prev_iters;
+                fused = steps_done > 0 && 2 * (hs->reorths - prev_reorths) >= steps_done;
+            }
+            if (fmt == CB_F64) fused = false;
+            prev_iters = hs->iters;
+            prev_reorths = hs->reorths;
+            step_e.fused = fused;
             double* wc = w;   // the current w (the residual r first)
             double* wn = w2;  // the buffer the next SpMV writes
             for (int j = 0; j < m; ++j) {
@@ -294,17 +315,26 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 Epi eh = sum_e;          // h_{1:j+1,j}
                 eh.out = hcol;
                 launch_project(fmt, V, j + 1, wc, part, active, eh, s);
-                Epi ec = step_e;         // omega, ||w||, step 7 test, maybe Givens
-                ec.mode = EPI_STEP_CHECK;
-                ec.j = j;
-                ec.extra = part_s;
-                ec.extra_G = Gs;
-                launch_subtract(fmt, V, j + 1, nullptr, hcol, wc, part, active, -1, ec, s);
-                Epi eu = step_e;         // u = V^T w, h += u
-                eu.mode = EPI_REORTH_PROJECT;
-                eu.out = u;
-                eu.j = j;
-                launch_project(fmt, V, j + 1, wc, part, reorth, eu, s);
+                // the first update; omega, ||w||, step 7 test, maybe Givens
+                Epi ex = step_e;
+                ex.out = u;
+                ex.j = j;
+                ex.extra = part_s;
+                ex.extra_G = Gs;
+                if (fused) {
+                    // fused with the second projection: u is formed whether or
+                    // not step 7 asks for it, and kept only if it does
+                    ex.mode = EPI_FUSED_CHECK;
+                    launch_subtract_project(fmt, V, j + 1, hcol, wc, part, active, ex, s);
+                } else {
+                    ex.mode = EPI_STEP_CHECK;
+                    launch_subtract(fmt, V, j + 1, nullptr, hcol, wc, part, active, -1, ex, s);
+                    Epi eu = step_e;     // u = V^T w, h += u
+                    eu.mode = EPI_REORTH_PROJECT;
+                    eu.out = u;
+                    eu.j = j;
+                    launch_project(fmt, V, j + 1, wc, part, reorth, eu, s);
+                }
                 Epi ef = step_e;         // ||w||, breakdown test, Givens
                 ef.mode = EPI_REORTH_FINISH;
                 ef.j = j;
