@@ -191,7 +191,12 @@ typedef struct cb_options {
     int32_t literal_breakdown; /* 1: step 12 compares h_{j+1,j} with eta * omega as
                                   printed; 0 (default): with eta times the norm before
                                   the re-orthogonalisation pass */
-    int32_t reserved;
+    int32_t fuse_updates;      /* first Gram-Schmidt update fused with the second
+                                  projection (formed speculatively, dropped when step 7
+                                  does not ask for it): 0 (default) per cycle, when the
+                                  last cycle re-orthogonalised at least half its steps
+                                  (never for a float64 basis); 1 never; 2 always.  The
+                                  arithmetic is the same either way. */
 } cb_options;
 
 typedef struct cb_result {
@@ -276,7 +281,8 @@ int64_t cbgmres_batch_workspace_bytes(int32_t n, int32_t m, int format);
  * results_host[i] receives system i's statistics (seconds = the batch's wall
  * time).  Synchronous.  Returns CB_ERR_INVALID_ARG / CB_ERR_WORKSPACE (nothing
  * launched) for a bad item, else CB_OK if every system converged, else the
- * status of the first that did not. */
+ * status of the first that did not.  Of the options, eta, max_iters and
+ * literal_breakdown apply (max_cycles and fuse_updates do not). */
 int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_options* opt,
                         cb_result* results_host, void* stream);
 

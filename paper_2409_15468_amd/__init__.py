@@ -43,7 +43,7 @@ class cb_csr(C.Structure):
 
 class cb_options(C.Structure):
     _fields_ = [("eta", C.c_double), ("max_iters", C.c_int32), ("max_cycles", C.c_int32),
-                ("literal_breakdown", C.c_int32), ("reserved", C.c_int32)]
+                ("literal_breakdown", C.c_int32), ("fuse_updates", C.c_int32)]
 
 
 class cb_result(C.Structure):
@@ -378,7 +378,8 @@ def cbgmres_workspace_bytes(n: int, m: int, fmt) -> int:
 
 def cbgmres_solve(A: DeviceCSR, b, x, m: int, tol: float, fmt="frsz2_32", eta: float = 0.0,
                   max_iters: int = 0, max_cycles: int = 0, literal_breakdown: bool = False,
-                  workspace=None, history_cap: int = 0, stream=None, check: bool = True):
+                  workspace=None, history_cap: int = 0, stream=None, check: bool = True,
+                  fuse_updates: int = 0):
     """Solve A x = b in place on x (x holds x0).  Returns (result dict,
     history numpy array of implicit relative residuals).  Solver outcomes
     (converged, not converged, non-finite) come back in result["status"];
@@ -389,7 +390,7 @@ def cbgmres_solve(A: DeviceCSR, b, x, m: int, tol: float, fmt="frsz2_32", eta: f
     _dev(b, torch.float64, "b")
     if x.numel() != A.n or b.numel() != A.n:
         raise ValueError("x and b must have n entries")
-    opt = cb_options(eta, max_iters, max_cycles, int(literal_breakdown), 0)
+    opt = cb_options(eta, max_iters, max_cycles, int(literal_breakdown), int(fuse_updates))
     res = cb_result()
     hist = np.zeros(max(history_cap, 1), np.float64)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()

@@ -220,6 +220,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     const int max_iters = (opt && opt->max_iters > 0) ? opt->max_iters : 20000;
     const int max_cycles = opt ? opt->max_cycles : 0;
     const int literal = opt ? opt->literal_breakdown : 0;
+    const int fuse_opt = opt ? opt->fuse_updates : 0;
 
     State* st = W.at<State>(W.L.state);
     int32_t* flag = W.at<int32_t>(W.L.flag);
@@ -299,6 +300,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 fused = steps_done > 0 && 2 * (hs->reorths - prev_reorths) >= steps_done;
             }
             if (fmt == CB_F64) fused = false;
+            if (fuse_opt == 1) fused = false;
+            if (fuse_opt == 2) fused = true;
             prev_iters = hs->iters;
             prev_reorths = hs->reorths;
             step_e.fused = fused;

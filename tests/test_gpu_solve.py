@@ -156,3 +156,18 @@ def test_tall_system_short_restart():
     res, x, _ = gpu_solve(A, b, 1, 1e-12, "float64")
     assert res["converged"] and res["iterations"] == 1
     np.testing.assert_allclose(x, b / 2, rtol=1e-13)
+
+
+@pytest.mark.parametrize("fmt", ["frsz2_21", "float32", "float64"])
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_fused_and_separate_first_update(fmt, fuse):
+    """The first Gram-Schmidt update run separately (fuse_updates=1) or fused
+    with the speculative second projection (2) solves the plain configuration
+    with the oracle's iteration count; the steps that do not need the second
+    pass drop the speculative projection."""
+    s = synth.plain_2d(N=64, seed=0)
+    res, x, _ = gpu_solve(s.A, s.b, 50, 1e-10, fmt, fuse_updates=fuse)
+    ref = oracle.gmres(s.A, s.b, 50, 1e-10, fmt)
+    assert res["converged"] and host_rrn(s.A, s.b, x) <= 1e-10 * (1 + 1e-6)
+    assert within_2pct(res["iterations"], ref.iterations), (res["iterations"], ref.iterations)
+    assert abs(res["reorths"] - ref.reorths) <= max(2, int(0.02 * ref.reorths))
