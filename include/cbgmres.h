@@ -8,7 +8,7 @@
  * basis vectors are stored compressed and decompressed inside the
  * Gram-Schmidt projections and the solution update; everything else (SpMV,
  * dot products, norms, Givens rotations, the solution) is FP64.  FRSZ2
- * (Section III) groups 32 consecutive values under their largest biased IEEE
+ * (Section IV) groups 32 consecutive values under their largest biased IEEE
  * exponent and keeps, per value, a sign bit and the leading l-1 bits of the
  * significand aligned to that exponent (Eq. 2).
  *
@@ -63,7 +63,7 @@ const char* cb_status_string(int status);
 const char* cb_last_error(void);
 
 /* ======================================================================
- * FRSZ2 codec (Section III-A compression steps 1-6, Section III-B
+ * FRSZ2 codec (Section IV-A compression steps 1-6, Section IV-B
  * decompression steps 1-4, storage layout of Eq. 3).
  *
  * Layout of a compressed vector of n values, nb = ceil(n/32) blocks:
@@ -74,7 +74,7 @@ const char* cb_last_error(void);
  *                code q at bits [q*l, (q+1)*l); a code is sign << (l-1) |
  *                floor(|x| / grid), i.e. the significand truncated to l-1
  *                bits after alignment to E.
- * The exponent and value arrays are separate (Section III-C, item 5).
+ * The exponent and value arrays are separate (Section IV-C, item 5).
  * A partial last block is encoded as if padded with +0.0.
  * ====================================================================== */
 

@@ -27,12 +27,12 @@
  * storage contract that the tests rely on. */
 enum { OR_F64 = 0, OR_F32 = 1, OR_F16 = 2, OR_FRSZ2_16 = 3, OR_FRSZ2_21 = 4, OR_FRSZ2_32 = 5 };
 
-#define OR_BS 32 /* FRSZ2 block size, fixed (Section III-C, item 2) */
+#define OR_BS 32 /* FRSZ2 block size, fixed (Section IV-C, item 2) */
 
 static int64_t nblocks_of(int64_t n) { return (n + OR_BS - 1) / OR_BS; }
 
 /* ------------------------------------------------------------------------ */
-/* FRSZ2 compression: the six steps of Section III-A, Eq. (1)-(2).           */
+/* FRSZ2 compression: the six steps of Section IV-A, Eq. (1)-(2).           */
 /* ------------------------------------------------------------------------ */
 
 /* Split an IEEE double into sign, biased exponent and 52 fraction bits
@@ -131,7 +131,7 @@ void or_frsz2_decode(const uint32_t* exps, const uint32_t* words, int64_t n, int
     }
 }
 
-/* Random-access decompression of value i by the four steps of Section III-B:
+/* Random-access decompression of value i by the four steps of Section IV-B:
  * read the block exponent and the code; split off the sign and count the
  * leading zeros k of the significand; drop them and the explicit 1, giving
  * the exponent e = E - k; merge sign, exponent and significand into IEEE bits.
@@ -322,7 +322,7 @@ void or_cgs_subtract(int64_t n, int j, const double* Vdec, int64_t ld, const dou
 
 /* ------------------------------------------------------------------------ */
 /* Restarted GMRES with classical Gram-Schmidt and one conditional           */
-/* re-orthogonalisation (Fig. 1), no preconditioner (M = I, Section IV-C).    */
+/* re-orthogonalisation (Fig. 1), no preconditioner (M = I, Section V-C).    */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {

@@ -360,7 +360,7 @@ __device__ __forceinline__ void load_tiles(Tile<FMT>* t, const BasisView& V, con
 }
 
 // ----------------------------------------------------------------- writing tiles
-// FRSZ2 code of v with block exponent field E (Section III-A steps 2-5).
+// FRSZ2 code of v with block exponent field E (Section IV-A steps 2-5).
 template <int L>
 __device__ __forceinline__ uint32_t frsz2_code(double v, uint32_t E) {
     const uint32_t hi = hi32(v), lo = lo32(v);

@@ -14,7 +14,7 @@ namespace dev {
 
 // Encode the lane's 8 values v (rows of Map<FMT>) of the tile at row tile0
 // into one column: values at `values`, FRSZ2 block exponents at `exps`
-// (Section III-A for frsz2; round-to-nearest-even casts for float32 and
+// (Section IV-A for frsz2; round-to-nearest-even casts for float32 and
 // float16; float64 stored as is).  Groups of rows at or past np are not
 // written.  Returns true if a stored value is not finite (for frsz2: a block
 // whose exponent field is 2047).

@@ -7,7 +7,7 @@ arithmetic (no compression, no Gram-Schmidt, no GMRES).  The one product it
 forms, b = A x*, uses scipy's CSR mat-vec as a library primitive so that both
 sides receive identical bytes.
 
-The paper evaluates on SuiteSparse CFD matrices (Section IV-B, Table 1).  Those
+The paper evaluates on SuiteSparse CFD matrices (Section V-B, Table 1).  Those
 are not available here; the convection-diffusion stencils below stand in for
 them (a 7-point 3D stencil has 6.94 nonzeros per row, the same density as the
 atmosmod matrices of Table 1).

@@ -4,7 +4,7 @@ Each pin checks the oracle against something other than itself: the
 hand-derived worked vectors (tests/golden/frsz2_worked.txt), the value
 definition of FRSZ2 as truncation onto the block's grid (Eq. 2 with "cut to
 length l" read as truncation), an independent LSB-first bit packer, the
-paper's four-step random-access decode route (Section III-B), brute force over
+paper's four-step random-access decode route (Section IV-B), brute force over
 every 16-bit code, and numpy's IEEE casts.
 """
 import os
