@@ -281,6 +281,46 @@ def precision_bench(cb, torch, steps, warmup):
     return out, s
 
 
+SWEEP_OPS = (0, 1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160,
+             192, 256)
+
+
+def intensity_sweep(cb, torch, n, formats, reps):
+    """The arithmetic-intensity sweep (the synthetic benchmark of Section
+    IV-C, 27 settings): one column of n values, N(0,1) scaled per 32-value
+    block by 10^u, u ~ U(-8, 0) (seed 2), read through each format's decoder
+    with `ops` FP64 multiply-adds per value."""
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(n) / np.sqrt(n) * np.repeat(10.0 ** rng.uniform(-8, 0, (n + 31) // 32), 32)[:n]
+    xd = torch.from_numpy(x).cuda()
+    del x
+    out = {}
+    s = torch.cuda.current_stream()
+    for fmt in formats:
+        V = cb.Basis.empty(fmt, n, 1)
+        cb.cb_basis_store(V, 0, xd)
+        part = torch.empty(cb.cb_intensity_groups(n), dtype=torch.float64, device="cuda")
+        bv = (cb.cb_basis_column_bytes(fmt, n) + 4 * cb.cb_basis_exponent_words(fmt, n)) / n
+        rows = []
+        for ops in SWEEP_OPS:
+            cb.cb_intensity_run(V, 0, ops, 0.999, 1e-3, part)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(reps):
+                cb.cb_intensity_run(V, 0, ops, 0.999, 1e-3, part)
+            e1.record(s)
+            e1.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / reps
+            rows.append({"ops": ops, "flop_per_byte": 2 * ops / bv, "seconds": t, "GBs": n * bv / t / 1e9,
+                         "GFLOPs": 2 * ops * n / t / 1e9})
+        out[fmt] = {"bytes_per_value": bv, "points": rows}
+        log(f"sweep {fmt}: ops=0 {rows[0]['GBs']:.0f} GB/s; ops=16 {rows[11]['GBs']:.0f} GB/s "
+            f"{rows[11]['GFLOPs']:.0f} GFLOP/s; ops=256 {rows[-1]['GFLOPs']:.0f} GFLOP/s")
+        del V, part
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,10 +337,11 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="microbench only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy 1 GiB once: the reference kernel for FETCH/WRITE_SIZE")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "serving", "precision"],
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "serving", "precision", "intensity"],
                     help="sweep: the n=1e6 solve + kernel microbench (default); serving: the "
                          "request stream through the continuous-batching server; precision: FP64 "
-                         "iterative refinement around a frsz2_16-basis GMRES at n=2^22")
+                         "iterative refinement around a frsz2_16-basis GMRES at n=2^22; intensity: the "
+                         "arithmetic-intensity sweep over 2^28 values per format")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -331,6 +372,19 @@ def main():
                                       f"arrivals {args.serve_rate}/s, n 32^2..128^3, formats f32/frsz2_16/21/32, "
                                       f"tol 1e-12..1e-8, m 30..100, HBM budget {args.serve_budget_gb} GB"},
                "serving": dict(sv, hw_queues=os.environ.get("GPU_MAX_HW_QUEUES", "default"))}
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "intensity":
+        fm = [f for f in args.micro_formats.split(",") if f] + ["float16"]
+        sw = intensity_sweep(cb, torch, 1 << 28, fm, args.micro_reps)
+        z = sw.get("frsz2_32", {}).get("points", [{}])[0]
+        rec = {"metric": "decompression read bandwidth vs arithmetic intensity (2^28 values)",
+               "value": z.get("GBs"), "unit": "GB/s", "n_gpus": 1, "steps": args.micro_reps, "warmup": 1,
+               "ms_per_step": z.get("seconds", 0) * 1e3, "higher_is_better": True, "scaling": "strong",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "2^28 values, N(0,1)/sqrt(n) x 10^U(-8,0) per 32-value block, seed 2; "
+                                      f"{len(SWEEP_OPS)} settings of 0..256 FP64 multiply-adds per value"},
+               "intensity": sw}
         print(json.dumps(rec), flush=True)
         return
     if args.workload == "precision":

@@ -241,6 +241,20 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
                      void* stream);
 
 /* ======================================================================
+ * Arithmetic-intensity sweep: the synthetic benchmark of Section IV-C
+ * (Fig. 3).  Column col of V is read through its format's decoder (the same
+ * tile loads and in-register decode as the Gram-Schmidt kernels) and every
+ * value y goes through `ops` dependent FP64 steps y <- y * a + b; workgroup g
+ * writes the sum of its results to partials[g] (device float64, at least
+ * cb_intensity_groups(V->n) entries).  Per value: the format's stored bytes
+ * read, 2 * ops FP64 operations.  Asynchronous.  CB_ERR_INVALID_ARG for a bad
+ * basis, column or ops < 0.
+ * ====================================================================== */
+int32_t cb_intensity_groups(int64_t n);
+int cb_intensity_run(const cb_basis* V, int32_t col, int32_t ops, double a, double b, double* partials,
+                     void* stream);
+
+/* ======================================================================
  * Batched solves of small systems (the serving path's packing of small
  * requests into one persistent launch).  Each system is solved by the method
  * of cbgmres_solve (Fig. 1 with restarts, Eq. 4 stop test, same options and

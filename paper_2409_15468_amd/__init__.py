@@ -91,6 +91,8 @@ SIGNATURES = {
     "cbgmres_batch_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
     "cbgmres_solve_batch": (C.c_int, [C.POINTER(cb_batch_item), _I32, C.POINTER(cb_options),
                                       C.POINTER(cb_result), _P]),
+    "cb_intensity_groups": (_I32, [_I64]),
+    "cb_intensity_run": (C.c_int, [C.POINTER(cb_basis), _I32, _I32, _D, _D, _P, _P]),
     "cb_server_create": (_P, [_SZ, C.c_int, C.c_int]),
     "cb_server_request_bytes": (_I64, [_I32, _I32, _I32, C.c_int]),
     "cb_server_submit": (C.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _I32, _D, C.c_int,
@@ -473,6 +475,22 @@ def cbgmres_solve_batch(systems, eta: float = 0.0, max_iters: int = 0, literal_b
         d = res[i].as_dict()
         out.append(d)
     return out
+
+
+# ---------------------------------------------------------------- intensity sweep
+def cb_intensity_groups(n: int) -> int:
+    return int(lib().cb_intensity_groups(n))
+
+
+def cb_intensity_run(V: Basis, col: int, ops: int, a: float, b: float, partials=None, stream=None):
+    """Read column col through its decoder, apply ops steps y <- y*a + b to
+    every value, return the per-workgroup sums (device tensor)."""
+    import torch
+    if partials is None:
+        partials = torch.empty(cb_intensity_groups(V.n), dtype=torch.float64, device=V.values.device)
+    d = V.desc()
+    _check(lib().cb_intensity_run(C.byref(d), col, ops, a, b, _ptr(partials), _stream(stream)), "cb_intensity_run")
+    return partials
 
 
 # ---------------------------------------------------------------- serving

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbgmres.so")
-SOURCES = ["api.hip", "basis.hip", "spmv.hip", "solver.hip", "batch.hip", "server.cpp"]
+SOURCES = ["api.hip", "basis.hip", "spmv.hip", "solver.hip", "batch.hip", "intensity.hip", "server.cpp"]
 HEADERS = ["cb_internal.hpp", "codec.hpp", "reduce.hpp", "epilogue.hpp", "tiles.hpp"]
 
 HIPCC_FLAGS = [
