@@ -266,6 +266,16 @@ def precision_bench(cb, torch, steps, warmup):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, r
 
+    # the inner relative tolerance of the refinement: 1e-4 is the reading the
+    # oracle pins; looser and tighter inner solves are timed beside it
+    inner = {}
+    for itol in (1e-2, 1e-6, 1e-8):
+        t_i, r_i = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, itol, 1e-12, "frsz2_16"))
+        inner[f"{itol:g}"] = {"seconds": t_i, "iterations": r_i["iterations"], "outer": r_i["restarts"],
+                              "converged": bool(r_i["converged"])}
+        log(f"precision ir inner_tol {itol:g}: {t_i * 1e3:.1f} ms, {r_i['iterations']} iterations, "
+            f"{r_i['restarts']} outer")
+    out["ir_inner_tol_sweep"] = inner
     t_ir, r_ir = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, 1e-4, 1e-12, "frsz2_16"))
     x_ir = x.cpu().numpy()
     t_64, r_64 = run(lambda: cb.cbgmres_solve(A, b, x, 100, 1e-12, "float64")[0])
