@@ -266,6 +266,9 @@ __device__ __forceinline__ bool reduce_tickets(const Epi& e, double* partials, d
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // a launch with a single group has no second round: its last workgroup
+    // reads its own group sums back
+    if (gridDim.y * ng == 1) return true;
     if (threadIdx.x == 0) flag = draw_last(e.counter, gridDim.y * (unsigned)ng);
     __syncthreads();
     return flag != 0;
