@@ -22,7 +22,9 @@ the same solve, scaled to the whole solve by basis-column work.
 Other workloads (--workload): `serving` runs the seeded request stream through
 the continuous-batching server (p50/p99 latency, solves/s); `precision` runs
 FP64 iterative refinement around a frsz2_16-basis GMRES(100) against the
-float64-basis solve on the 2^22-row banded system.
+float64-basis solve on the 2^22-row banded system; `intensity` the
+arithmetic-intensity sweep; `adaptive` the solve with its basis format picked
+by probing candidates before the first restart, against every fixed format.
 
 Prints one JSON line.
 """
@@ -292,6 +294,58 @@ def precision_bench(cb, torch, steps, warmup):
     return out, s
 
 
+def adaptive_bench(cb, torch, grid, steps, warmup, probe_steps):
+    """Basis format picked by probing before the first restart against every
+    fixed format, on the sweep system (GMRES(100), tol 1e-10, x0 = 0).  The
+    probing solve's time includes its probes."""
+    import synth
+    s = synth.sweep_3d(N=grid, seed=1)
+    A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    b = torch.from_numpy(s.b).cuda()
+    x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    m, tol = 100, 1e-10
+    cands = ["frsz2_32", "float32", "float16", "frsz2_16"]
+    out = {"candidates": cands, "probe_steps": probe_steps, "fixed": {}}
+
+    def run(fn):
+        r = None
+        for _ in range(warmup):
+            x.zero_()
+            r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    for fmt in ("float64",) + tuple(cands):
+        tt, r = run(lambda: cb.cbgmres_solve(A, b, x, m, tol, fmt)[0])
+        out["fixed"][fmt] = {"seconds": tt, "iterations": r["iterations"], "converged": bool(r["converged"])}
+        log(f"adaptive: fixed {fmt}: {tt * 1e3:.1f} ms, {r['iterations']} iterations")
+    ws = torch.empty(cb.cbgmres_auto_workspace_bytes(s.A.n, m, probe_steps, cands), dtype=torch.uint8,
+                     device="cuda")
+    picks = []
+
+    def auto():
+        r, _ = cb.cbgmres_solve_auto(A, b, x, m, tol, cands, probe_steps, workspace=ws)
+        picks.append(cands[r["chosen"]])
+        return r
+    tt, r = run(auto)
+    rrn = float(np.linalg.norm(s.b - s.A.scipy() @ x.cpu().numpy()) / np.linalg.norm(s.b))
+    best = min(out["fixed"].values(), key=lambda v: v["seconds"])["seconds"]
+    out["auto"] = {"seconds": tt, "picks": picks, "probe_seconds": r["probe_seconds"],
+                   "probe_rel_residual": r["probe_rel_residual"], "probe_rate": r["probe_rate"],
+                   "continuation_iterations": r["solve"]["iterations"],
+                   "total_steps": sum(r["probe_steps"]) + r["solve"]["iterations"],
+                   "converged": bool(r["solve"]["converged"]), "rel_residual": rrn,
+                   "vs_best_fixed": tt / best}
+    log(f"adaptive: auto {tt * 1e3:.1f} ms (best fixed {best * 1e3:.1f} ms), picks {picks}, "
+        f"probe rates {[round(v, 1) for v in r['probe_rate']]}")
+    return out, s
+
+
 SWEEP_OPS = (0, 1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160,
              192, 256)
 
@@ -348,11 +402,14 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="microbench only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy 1 GiB once: the reference kernel for FETCH/WRITE_SIZE")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "serving", "precision", "intensity"],
+    ap.add_argument("--probe-steps", type=int, default=20, help="probe length of the adaptive workload")
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "serving", "precision", "intensity", "adaptive"],
                     help="sweep: the n=1e6 solve + kernel microbench (default); serving: the "
                          "request stream through the continuous-batching server; precision: FP64 "
                          "iterative refinement around a frsz2_16-basis GMRES at n=2^22; intensity: the "
-                         "arithmetic-intensity sweep over 2^28 values per format")
+                         "arithmetic-intensity sweep over 2^28 values per format; adaptive: the basis "
+                         "format picked by probing against every fixed format")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -408,6 +465,18 @@ def main():
                "config": {"workload": f"banded random n={ps.A.n}, nnz={ps.A.nnz} (27 per row, |i-j|<=1000, "
                                       "diagonal 1.2 x row sum, seed 3), tol 1e-12"},
                "precision": pv}
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "adaptive":
+        av, s = adaptive_bench(cb, torch, args.grid, args.steps, args.warmup, args.probe_steps)
+        rec = {"metric": "time-to-1e-10 residual, basis format picked by probing vs fixed formats",
+               "value": av["auto"]["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": av["auto"]["seconds"] * 1e3, "higher_is_better": False,
+               "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"cd3d N={args.grid} (n={s.A.n}, nnz={s.A.nnz}), GMRES(100), tol 1e-10, "
+                                      f"x0=0; candidates {','.join(av['candidates'])}, "
+                                      f"{args.probe_steps}-step probes"},
+               "adaptive": av}
         print(json.dumps(rec), flush=True)
         return
     m, tol = 100, 1e-10

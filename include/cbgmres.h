@@ -241,6 +241,66 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
                      void* stream);
 
 /* ======================================================================
+ * Basis format chosen before the first restart (the autotuning the paper's
+ * conclusions propose, Section VIII: observe the convergence per unit time of
+ * several candidate methods, then continue with the best one).
+ *
+ * Each candidate format runs a probe -- one GMRES(probe_steps) cycle from the
+ * caller's x0, capped at probe_steps Arnoldi steps -- and is scored by its
+ * rate: ln(rel_residual0 / rel_residual) / seconds, where rel_residual is the
+ * explicit ||b - A x|| / ||b|| after the probe, rel_residual0 that of x0 and
+ * seconds the probe's wall time.  A probe that did not lower the residual, or
+ * met Inf/NaN, scores -inf; one that reached ||b - A x|| = 0 scores +inf.
+ * The first candidate with the highest rate is chosen (cb_auto_pick), and
+ * the solve continues with GMRES(m) in that format from that probe's
+ * iterate.  A probe that meets tol ends the probing and is chosen.  One
+ * untimed Arnoldi step with the first candidate runs before the probes so
+ * that one-time costs (code loading, host buffers) fall outside them.
+ * ====================================================================== */
+#define CB_AUTO_MAX_CANDIDATES 8
+
+typedef struct cb_auto_result {
+    int32_t chosen;          /* index into candidates of the format continued with */
+    int32_t chosen_format;   /* cb_basis_format of that candidate */
+    int32_t probed;          /* probes run (fewer than candidates when one met tol) */
+    int32_t status;          /* cb_status of the call */
+    double rel_residual0;    /* ||b - A x0|| / ||b|| */
+    int32_t probe_steps[CB_AUTO_MAX_CANDIDATES];        /* Arnoldi steps per probe */
+    double probe_rel_residual[CB_AUTO_MAX_CANDIDATES];  /* explicit, after each probe */
+    double probe_seconds[CB_AUTO_MAX_CANDIDATES];       /* wall time per probe */
+    double probe_rate[CB_AUTO_MAX_CANDIDATES];          /* the score above */
+    double seconds;          /* wall time of the whole call */
+    cb_result solve;         /* the continuation in the chosen format */
+} cb_auto_result;
+
+/* The pick rule on its own (pure host code, no GPU): the index of the first
+ * of count candidates with the highest rate ln(rel0 / rel[i]) / seconds[i],
+ * scored as above; -1 if count < 1 or a pointer is NULL. */
+int32_t cb_auto_pick(double rel0, const double* rel_host, const double* seconds_host, int32_t count);
+
+/* Device workspace bytes cbgmres_solve_auto needs: the largest solver
+ * workspace over the candidates at restart lengths m and probe_steps, plus
+ * three float64[n] vectors (x0, the probe iterate, the best iterate).  -1 for
+ * bad arguments. */
+int64_t cbgmres_auto_workspace_bytes(int32_t n, int32_t m, int32_t probe_steps,
+                                     const int32_t* candidates_host, int32_t count);
+
+/* Solve A x = b with the basis format picked by probing.  x, b, m, tol, opt,
+ * history_host/history_cap are as for cbgmres_solve; opt applies to the
+ * probes (except max_iters and max_cycles) and to the continuation.
+ * candidates_host holds 1..CB_AUTO_MAX_CANDIDATES basis formats;
+ * 1 <= probe_steps <= 512.  workspace: NULL (allocated and freed here) or at
+ * least cbgmres_auto_workspace_bytes.  Total Arnoldi steps = the sum of
+ * probe_steps[] plus solve.iterations.  Synchronous.  Returns the
+ * continuation's status; CB_ERR_INVALID_ARG / CB_ERR_WORKSPACE with nothing
+ * launched for bad arguments. */
+int cbgmres_solve_auto(const cb_csr* A, const double* b, double* x, int32_t m, double tol,
+                       const int32_t* candidates_host, int32_t count, int32_t probe_steps,
+                       const cb_options* opt, void* workspace, size_t workspace_bytes,
+                       double* history_host, int64_t history_cap, cb_auto_result* result_host,
+                       void* stream);
+
+/* ======================================================================
  * Arithmetic-intensity sweep: the synthetic benchmark of Section IV-C
  * (Fig. 3).  Column col of V is read through its format's decoder (the same
  * tile loads and in-register decode as the Gram-Schmidt kernels) and every

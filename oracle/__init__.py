@@ -297,3 +297,39 @@ def dense_solve(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     if lib().or_dense_solve(A.shape[0], _p(A), _p(x)):
         raise np.linalg.LinAlgError("singular")
     return x
+
+
+# ---------------------------------------------------------------- format chosen by probing
+# The autotuning named in the paper's conclusions (Section VIII): run each
+# candidate method for a short probe, measure its convergence per unit time,
+# continue with the best.  The reading used here: a probe is a GMRES(p) run
+# from x0 capped at p Arnoldi steps; its rate is the natural-log decrease of
+# the explicit relative residual per second of wall time; the first candidate
+# with the highest rate wins; a probe that met the tolerance wins outright.
+def auto_rate(rel0: float, rel: float, seconds: float) -> float:
+    """ln(rel0 / rel) / seconds; -inf when the probe did not lower the
+    residual or produced Inf/NaN; +inf when it reached a zero residual."""
+    import math
+    if not math.isfinite(rel) or rel < 0.0 or not rel < rel0:
+        return -math.inf
+    if rel == 0.0 or not seconds > 0.0:
+        return math.inf
+    return math.log(rel0 / rel) / seconds
+
+
+def auto_pick(rel0: float, rel, seconds) -> int:
+    """Index of the first candidate with the highest auto_rate."""
+    rates = [auto_rate(rel0, r, t) for r, t in zip(rel, seconds)]
+    best = 0
+    for i, r in enumerate(rates):
+        if r > rates[best]:
+            best = i
+    return best
+
+
+def auto_probe(A, b, x0, fmt, probe_steps: int, tol: float, eta: float = 0.7071067811865476,
+               literal_breakdown: bool = False) -> GmresResult:
+    """One candidate's probe: GMRES(probe_steps) from x0, at most probe_steps
+    Arnoldi steps; rel_residual is the explicit residual after it."""
+    return gmres(A, b, probe_steps, tol, fmt, x0=x0, eta=eta, max_iters=probe_steps,
+                 literal_breakdown=literal_breakdown)

@@ -56,6 +56,27 @@ class cb_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+CB_AUTO_MAX_CANDIDATES = 8
+
+
+class cb_auto_result(C.Structure):
+    _K = CB_AUTO_MAX_CANDIDATES
+    _fields_ = [("chosen", C.c_int32), ("chosen_format", C.c_int32), ("probed", C.c_int32),
+                ("status", C.c_int32), ("rel_residual0", C.c_double),
+                ("probe_steps", C.c_int32 * _K), ("probe_rel_residual", C.c_double * _K),
+                ("probe_seconds", C.c_double * _K), ("probe_rate", C.c_double * _K),
+                ("seconds", C.c_double), ("solve", cb_result)]
+
+    def as_dict(self) -> dict:
+        k = self.probed
+        return {"chosen": self.chosen, "chosen_format": self.chosen_format, "probed": k,
+                "status": self.status, "rel_residual0": self.rel_residual0,
+                "probe_steps": list(self.probe_steps[:k]),
+                "probe_rel_residual": list(self.probe_rel_residual[:k]),
+                "probe_seconds": list(self.probe_seconds[:k]), "probe_rate": list(self.probe_rate[:k]),
+                "seconds": self.seconds, "solve": self.solve.as_dict()}
+
+
 class cb_batch_item(C.Structure):
     _fields_ = [("A", cb_csr), ("b", C.c_void_p), ("x", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t), ("m", C.c_int32), ("format", C.c_int32),
@@ -86,6 +107,11 @@ SIGNATURES = {
                                 _P, _SZ, _P, _I64, C.POINTER(cb_result), _P]),
     "cbgmres_ir_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _D, C.c_int, _I32,
                                    C.POINTER(cb_result), _P]),
+    "cb_auto_pick": (_I32, [_D, _P, _P, _I32]),
+    "cbgmres_auto_workspace_bytes": (_I64, [_I32, _I32, _I32, _P, _I32]),
+    "cbgmres_solve_auto": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _P, _I32, _I32,
+                                     C.POINTER(cb_options), _P, _SZ, _P, _I64,
+                                     C.POINTER(cb_auto_result), _P]),
     "cbgmres_batch_max_n": (_I32, []),
     "cbgmres_batch_max_restart": (_I32, []),
     "cbgmres_batch_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
@@ -421,6 +447,58 @@ def cbgmres_ir_solve(A: DeviceCSR, b, x, m: int, inner_tol: float, tol: float, f
     out = res.as_dict()
     out["status"] = st
     return out
+
+
+def cb_auto_pick(rel0: float, rel, seconds) -> int:
+    """Index of the first candidate with the highest convergence rate
+    ln(rel0 / rel[i]) / seconds[i] (host-only rule)."""
+    import numpy as np
+    r = np.ascontiguousarray(rel, np.float64)
+    s = np.ascontiguousarray(seconds, np.float64)
+    if r.size != s.size:
+        raise ValueError("rel and seconds differ in length")
+    return int(lib().cb_auto_pick(rel0, r.ctypes.data_as(C.c_void_p), s.ctypes.data_as(C.c_void_p), r.size))
+
+
+def _formats_array(candidates):
+    fm = (C.c_int32 * max(1, len(candidates)))(*[_fmt(c) for c in candidates])
+    return fm
+
+
+def cbgmres_auto_workspace_bytes(n: int, m: int, probe_steps: int, candidates) -> int:
+    fm = _formats_array(candidates)
+    return int(lib().cbgmres_auto_workspace_bytes(n, m, probe_steps, C.cast(fm, C.c_void_p), len(candidates)))
+
+
+def cbgmres_solve_auto(A: DeviceCSR, b, x, m: int, tol: float,
+                       candidates=("frsz2_32", "float32", "float16"), probe_steps: int = 20,
+                       eta: float = 0.0, max_iters: int = 0, max_cycles: int = 0,
+                       literal_breakdown: bool = False, fuse_updates: int = 0, workspace=None,
+                       history_cap: int = 0, stream=None, check: bool = True):
+    """Solve A x = b in place on x with the basis format picked by probing
+    each candidate for probe_steps Arnoldi steps from x0.  Returns (result
+    dict with the probes and the continuation under "solve", history of the
+    continuation's implicit relative residuals)."""
+    import numpy as np
+    import torch
+    _dev(x, torch.float64, "x")
+    _dev(b, torch.float64, "b")
+    if x.numel() != A.n or b.numel() != A.n:
+        raise ValueError("x and b must have n entries")
+    fm = _formats_array(candidates)
+    opt = cb_options(eta, max_iters, max_cycles, int(literal_breakdown), int(fuse_updates))
+    res = cb_auto_result()
+    hist = np.zeros(max(history_cap, 1), np.float64)
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    d = A.desc()
+    st = lib().cbgmres_solve_auto(C.byref(d), _ptr(b), _ptr(x), m, tol, C.cast(fm, C.c_void_p), len(candidates),
+                                  probe_steps, C.byref(opt), _ptr(workspace), nbytes,
+                                  hist.ctypes.data_as(C.c_void_p), history_cap, C.byref(res), _stream(stream))
+    if check and st not in (CB_OK, CB_ERR_NOT_CONVERGED, CB_ERR_NONFINITE):
+        _check(st, "cbgmres_solve_auto")
+    out = res.as_dict()
+    out["status"] = st
+    return out, hist[:min(history_cap, res.solve.iterations)]
 
 
 def cbgmres_batch_max_n() -> int:

@@ -20,6 +20,7 @@
 // the cycle has ended read the control block and return at once.  The host
 // waits once per cycle, after the explicit residual of the restart (step 1 /
 // 18, Eq. 4) has been evaluated, to learn whether to stop.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -498,6 +499,177 @@ done:
     acc.seconds = now_s() - t0;
     if (result_host) *result_host = acc;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// Basis format picked by probing before the first restart.
+
+static double auto_rate(double rel0, double rel, double seconds) {
+    if (!std::isfinite(rel) || rel < 0.0 || !(rel < rel0)) return -INFINITY;
+    if (rel == 0.0 || !(seconds > 0.0)) return INFINITY;
+    return std::log(rel0 / rel) / seconds;
+}
+
+int32_t cb_auto_pick(double rel0, const double* rel_host, const double* seconds_host, int32_t count) {
+    if (count < 1 || !rel_host || !seconds_host) return -1;
+    int32_t best = 0;
+    double best_rate = auto_rate(rel0, rel_host[0], seconds_host[0]);
+    for (int32_t i = 1; i < count; ++i) {
+        const double r = auto_rate(rel0, rel_host[i], seconds_host[i]);
+        if (r > best_rate) {
+            best = i;
+            best_rate = r;
+        }
+    }
+    return best;
+}
+
+static int64_t auto_solver_bytes(int32_t n, int32_t m, int32_t p, const int32_t* cand, int32_t count) {
+    int64_t bytes = 0;
+    for (int32_t i = 0; i < count; ++i)
+        bytes = std::max({bytes, layout_of(n, m, cand[i]).total, layout_of(n, p, cand[i]).total});
+    return al(bytes);
+}
+
+int64_t cbgmres_auto_workspace_bytes(int32_t n, int32_t m, int32_t probe_steps,
+                                     const int32_t* candidates_host, int32_t count) {
+    if (n < 1 || m < 1 || m > kMaxRestart || probe_steps < 1 || probe_steps > kMaxRestart ||
+        !candidates_host || count < 1 || count > CB_AUTO_MAX_CANDIDATES)
+        return -1;
+    for (int32_t i = 0; i < count; ++i)
+        if (!valid_format(candidates_host[i])) return -1;
+    return auto_solver_bytes(n, m, probe_steps, candidates_host, count) + 3 * al(padded_rows(n) * 8) + 256;
+}
+
+int cbgmres_solve_auto(const cb_csr* A, const double* b, double* x, int32_t m, double tol,
+                       const int32_t* candidates_host, int32_t count, int32_t probe_steps,
+                       const cb_options* opt, void* workspace, size_t workspace_bytes,
+                       double* history_host, int64_t history_cap, cb_auto_result* result_host,
+                       void* stream) {
+    if (!candidates_host || count < 1 || count > CB_AUTO_MAX_CANDIDATES)
+        return fail(CB_ERR_INVALID_ARG, "candidate count must be in [1, %d]", CB_AUTO_MAX_CANDIDATES);
+    if (int e = check_solve_args(A, b, x, m, tol, candidates_host[0])) return e;
+    for (int32_t i = 0; i < count; ++i)
+        if (!valid_format(candidates_host[i]))
+            return fail(CB_ERR_INVALID_ARG, "unknown basis format %d", candidates_host[i]);
+    if (probe_steps < 1 || probe_steps > kMaxRestart)
+        return fail(CB_ERR_INVALID_ARG, "probe_steps=%d out of range [1, %d]", probe_steps, kMaxRestart);
+    const int n = A->n;
+    const int64_t total = cbgmres_auto_workspace_bytes(n, m, probe_steps, candidates_host, count);
+    if (workspace && (int64_t)workspace_bytes < total)
+        return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", workspace_bytes, (long long)total);
+    const double t0 = now_s();
+    hipStream_t s = (hipStream_t)stream;
+    struct Owned {
+        void* p = nullptr;
+        hipStream_t s;
+        ~Owned() {
+            if (p) {
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(p);
+            }
+        }
+    } owned{nullptr, s};
+    Ws W;
+    if (workspace) {
+        W.base = static_cast<unsigned char*>(workspace);
+    } else {
+        CB_HIP(hipMalloc(&owned.p, (size_t)total));
+        W.base = static_cast<unsigned char*>(owned.p);
+    }
+    const int64_t solver_bytes = auto_solver_bytes(n, m, probe_steps, candidates_host, count);
+    const int64_t vec = al(padded_rows(n) * 8);
+    double* x0 = reinterpret_cast<double*>(W.base + solver_bytes);
+    double* xp = reinterpret_cast<double*>(W.base + solver_bytes + vec);      // the probe's iterate
+    double* xb = reinterpret_cast<double*>(W.base + solver_bytes + 2 * vec);  // the best probe's
+    double* scal = reinterpret_cast<double*>(W.base + solver_bytes + 3 * vec);
+
+    cb_auto_result out;
+    memset(&out, 0, sizeof out);
+    out.chosen_format = candidates_host[0];
+    out.rel_residual0 = -1.0;
+    out.solve.rel_residual = -1.0;
+    out.solve.implicit_rel_residual = -1.0;
+    auto finish = [&](int status) {
+        out.status = status;
+        out.solve.status = status;
+        out.seconds = now_s() - t0;
+        if (result_host) *result_host = out;
+        return status;
+    };
+
+    // ||b|| and ||b - A x0||
+    W.L = layout_of(n, m, candidates_host[0]);
+    double* part = W.at<double>(W.L.part);
+    double* hv = static_cast<double*>(g_pinned.get(sizeof(State) + (size_t)std::max(m, probe_steps) * 8 + 64));
+    if (!hv) return fail(CB_ERR_HIP, "hipHostMalloc failed");
+    enqueue_sumsq(b, n, part, scal, s);
+    launch_spmv(*A, x, b, xp, part, 1, nullptr, s);
+    launch_reduce(part, spmv_groups(n, A->nnz), 1, scal + 1, 0, nullptr, s);
+    CB_HIP(hipMemcpyAsync(hv, scal, 16, hipMemcpyDeviceToHost, s));
+    CB_HIP(hipStreamSynchronize(s));
+    const double nb = std::sqrt(hv[0]);
+    if (nb == 0.0) {  // b = 0: x = 0 solves it exactly
+        launch_fill(x, 0.0, n, s);
+        CB_HIP(hipStreamSynchronize(s));
+        out.rel_residual0 = 0.0;
+        out.solve.converged = 1;
+        out.solve.rel_residual = 0.0;
+        return finish(CB_OK);
+    }
+    const double rel0 = std::sqrt(hv[1]) / nb;
+    out.rel_residual0 = rel0;
+    out.solve.rel_residual = rel0;
+    if (!std::isfinite(rel0)) return finish(CB_ERR_NONFINITE);
+    if (rel0 <= tol) {
+        out.solve.converged = 1;
+        return finish(CB_OK);
+    }
+    CB_HIP(hipMemcpyAsync(x0, x, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+
+    // untimed warm-up step, then one probe per candidate
+    cb_options po{0.0, 1, 0, 0, 0};
+    if (opt) {
+        po.eta = opt->eta;
+        po.literal_breakdown = opt->literal_breakdown;
+        po.fuse_updates = opt->fuse_updates;
+    }
+    CB_HIP(hipMemcpyAsync(xp, x0, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    W.L = layout_of(n, 1, candidates_host[0]);
+    if (solve_impl(*A, b, xp, 1, tol, candidates_host[0], &po, W, nullptr, 0, nullptr, s) == CB_ERR_HIP)
+        return finish(CB_ERR_HIP);
+    po.max_iters = probe_steps;
+    double rel[CB_AUTO_MAX_CANDIDATES], secs[CB_AUTO_MAX_CANDIDATES];
+    for (int32_t i = 0; i < count; ++i) {
+        const int c = candidates_host[i];
+        CB_HIP(hipMemcpyAsync(xp, x0, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+        CB_HIP(hipStreamSynchronize(s));
+        W.L = layout_of(n, probe_steps, c);
+        cb_result pr;
+        const int st = solve_impl(*A, b, xp, probe_steps, tol, c, &po, W, nullptr, 0, &pr, s);
+        if (st == CB_ERR_HIP) return finish(CB_ERR_HIP);
+        rel[i] = st == CB_ERR_NONFINITE ? NAN : pr.rel_residual;
+        secs[i] = pr.seconds;
+        out.probe_steps[i] = pr.iterations;
+        out.probe_rel_residual[i] = rel[i];
+        out.probe_seconds[i] = secs[i];
+        out.probe_rate[i] = auto_rate(rel0, rel[i], secs[i]);
+        out.probed = i + 1;
+        // keep the best probe's iterate: swap the buffers when this one leads
+        if (pr.converged || cb_auto_pick(rel0, rel, secs, i + 1) == i) {
+            std::swap(xp, xb);
+            out.chosen = i;
+        }
+        if (pr.converged) break;
+    }
+    out.chosen_format = candidates_host[out.chosen];
+
+    // continue from the chosen probe's iterate in its format
+    CB_HIP(hipMemcpyAsync(x, xb, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    W.L = layout_of(n, m, out.chosen_format);
+    const int st = solve_impl(*A, b, x, m, tol, out.chosen_format, opt, W, history_host, history_cap,
+                              &out.solve, s);
+    return finish(st);
 }
 
 }  // extern "C"

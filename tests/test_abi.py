@@ -114,3 +114,29 @@ def test_batch_arguments_without_device_work():
     item[0].tol = 0.0
     assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_INVALID_ARG
     assert L.cbgmres_solve_batch(item, 0, None, res, None) == cb.CB_OK
+
+
+def test_auto_solve_arguments_without_device_work():
+    """cbgmres_solve_auto rejects bad candidate lists, probe lengths and
+    workspaces before any device work.  Pointers here are never dereferenced."""
+    L = cb.lib()
+    res = cb.cb_auto_result()
+    A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    need = cb.cbgmres_auto_workspace_bytes(1000, 30, 10, ["frsz2_32", "float16"])
+    assert need >= max(cb.cbgmres_workspace_bytes(1000, 30, f) for f in ("frsz2_32", "float16")) + 3 * 8 * 1000
+    assert cb.cbgmres_auto_workspace_bytes(1000, 30, 0, ["frsz2_32"]) == -1
+    assert cb.cbgmres_auto_workspace_bytes(1000, 30, 10, [9]) == -1
+    assert cb.cbgmres_auto_workspace_bytes(1000, 30, 10, ["float64"] * 9) == -1
+
+    def call(cands, probe, ws_bytes=need, m=30, tol=1e-8):
+        fm = (C.c_int32 * max(1, len(cands)))(*cands)
+        return L.cbgmres_solve_auto(C.byref(A), 256, 256, m, tol, C.cast(fm, C.c_void_p), len(cands), probe,
+                                    None, 256, ws_bytes, None, 0, C.byref(res), None)
+    assert call([], 10) == cb.CB_ERR_INVALID_ARG
+    assert call([5] * 9, 10) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 9], 10) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 2], 0) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 2], 513) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 2], 10, m=0) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 2], 10, tol=0.0) == cb.CB_ERR_INVALID_ARG
+    assert call([5, 2], 10, ws_bytes=need - 1) == cb.CB_ERR_WORKSPACE

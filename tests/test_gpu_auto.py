@@ -1,0 +1,164 @@
+"""Parity of cbgmres_solve_auto (basis format picked by probing, the
+autotuning of the paper's conclusions, Section VIII) against the oracle.
+
+The pick depends on measured wall time, so several choices are correct: the
+tests compare what is unique -- every probe's step count and explicit
+residual against the oracle's probe of the same format from the same x0, the
+continuation against the oracle's GMRES(m) from the oracle's probe iterate of
+the chosen format -- and check that the reported choice is the one the pick
+rule makes from the reported rates."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2409_15468_amd as cb
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+UNIT = {"float64": 2.0 ** -53, "float32": 2.0 ** -24, "float16": 2.0 ** -11,
+        "frsz2_16": 2.0 ** -14, "frsz2_21": 2.0 ** -19, "frsz2_32": 2.0 ** -30}
+NAMES = {v: k for k, v in cb.FORMATS.items()}
+
+
+def gpu_auto(A, b, m, tol, cands, probe, x0=None, workspace=False, **kw):
+    Ad = cb.DeviceCSR.from_host(A.row_ptr, A.col, A.val)
+    bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    xd = torch.zeros(A.n, dtype=torch.float64, device="cuda") if x0 is None else \
+        torch.from_numpy(np.array(x0, dtype=np.float64)).cuda()
+    ws = None
+    if workspace:
+        nbytes = cb.cbgmres_auto_workspace_bytes(A.n, m, probe, cands)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    res, hist = cb.cbgmres_solve_auto(Ad, bd, xd, m, tol, cands, probe, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    return res, xd.cpu().numpy(), hist
+
+
+def host_rrn(A, b, x):
+    return np.linalg.norm(b - A.scipy() @ x) / np.linalg.norm(b)
+
+
+def check_choice(res):
+    k = res["probed"]
+    assert 1 <= k and res["chosen"] < k
+    assert res["chosen_format"] == cb.FORMATS[res["cands"][res["chosen"]]]
+    last = res["probe_rel_residual"][k - 1]
+    if last <= res["tol"]:  # a probe that met tol ends the probing and wins
+        assert res["chosen"] == k - 1
+    else:
+        assert res["chosen"] == cb.cb_auto_pick(res["rel_residual0"], res["probe_rel_residual"],
+                                                res["probe_seconds"])
+    for r, t, rate in zip(res["probe_rel_residual"], res["probe_seconds"], res["probe_rate"]):
+        assert t > 0
+        assert rate == pytest.approx(oracle.auto_rate(res["rel_residual0"], r, t), rel=1e-12)
+
+
+def test_probes_and_continuation_match_oracle():
+    """All six formats probed for 15 steps on the plain 2D system (n = 4096);
+    each probe agrees with the oracle's; the solve continues in the chosen
+    format as the oracle does from its own probe iterate."""
+    s = synth.plain_2d(N=64, seed=0)
+    cands = list(oracle.FORMATS)
+    res, x, hist = gpu_auto(s.A, s.b, 40, 1e-10, cands, 15, history_cap=4000)
+    res["cands"], res["tol"] = cands, 1e-10
+    print({k: res[k] for k in ("chosen", "probe_steps", "probe_rel_residual", "probe_seconds")},
+          res["solve"]["iterations"])
+    assert res["status"] == 0 and res["probed"] == 6
+    check_choice(res)
+    assert res["rel_residual0"] == pytest.approx(1.0, rel=1e-14)  # x0 = 0
+    probes = {}
+    for i, fmt in enumerate(cands):
+        pr = oracle.auto_probe(s.A, s.b, np.zeros(s.A.n), fmt, 15, 1e-10)
+        probes[fmt] = pr
+        assert res["probe_steps"][i] == pr.iterations == 15
+        assert res["probe_rel_residual"][i] == pytest.approx(pr.rel_residual, rel=max(1e-8, 64 * UNIT[fmt]))
+    fmt = cands[res["chosen"]]
+    ref = oracle.gmres(s.A, s.b, 40, 1e-10, fmt, x0=probes[fmt].x)
+    sv = res["solve"]
+    assert sv["converged"] and sv["status"] == 0
+    assert host_rrn(s.A, s.b, x) <= 1e-10 * (1 + 1e-6)
+    slack = 0.10 if fmt == "float16" else 0.02  # an 11-bit basis amplifies last-bit differences
+    assert abs(sv["iterations"] - ref.iterations) <= max(1, int(np.ceil(slack * ref.iterations)))
+    ref64 = oracle.gmres(s.A, s.b, 40, 1e-10, "float64")
+    assert np.linalg.norm(x - ref64.x) / np.linalg.norm(ref64.x) < 1e-6
+    assert hist.size == sv["iterations"]
+
+
+@pytest.mark.parametrize("fmt", list(oracle.FORMATS))
+def test_single_candidate_replays_oracle(fmt):
+    """With one candidate the call is deterministic: probe then GMRES(m) in
+    that format, on a 3D system with a ragged row count (n = 17^3)."""
+    A = synth.convection_diffusion(17, 3, (10.0, 5.0, 2.0))
+    rng = np.random.default_rng(11)
+    b = synth.rhs_from_solution(A, rng.uniform(-1, 1, A.n))
+    x0 = rng.standard_normal(A.n) * 0.1
+    res, x, _ = gpu_auto(A, b, 25, 1e-9, [fmt], 9, x0=x0)
+    res["cands"], res["tol"] = [fmt], 1e-9
+    check_choice(res)
+    pr = oracle.auto_probe(A, b, x0, fmt, 9, 1e-9)
+    ref = oracle.gmres(A, b, 25, 1e-9, fmt, x0=pr.x)
+    assert res["probe_steps"][0] == pr.iterations == 9
+    assert res["probe_rel_residual"][0] == pytest.approx(pr.rel_residual, rel=max(1e-8, 64 * UNIT[fmt]))
+    assert res["rel_residual0"] == pytest.approx(np.linalg.norm(b - A.scipy() @ x0) / np.linalg.norm(b),
+                                                 rel=1e-12)
+    sv = res["solve"]
+    assert sv["converged"] and host_rrn(A, b, x) <= 1e-9 * (1 + 1e-6)
+    slack = 0.10 if fmt == "float16" else 0.02
+    assert abs(sv["iterations"] - ref.iterations) <= max(1, int(np.ceil(slack * ref.iterations)))
+    assert sv["restarts"] == ref.restarts or fmt == "float16"
+
+
+def test_probe_meeting_tol_ends_probing():
+    s = synth.plain_2d(N=32, seed=2)
+    res, x, _ = gpu_auto(s.A, s.b, 30, 1e-3, ["float16", "frsz2_32", "float64"], 200)
+    res["cands"], res["tol"] = ["float16", "frsz2_32", "float64"], 1e-3
+    assert res["probed"] == 1 and res["chosen"] == 0 and res["chosen_format"] == cb.FORMATS["float16"]
+    check_choice(res)
+    pr = oracle.auto_probe(s.A, s.b, np.zeros(s.A.n), "float16", 200, 1e-3)
+    assert pr.converged and res["probe_steps"][0] == pr.iterations
+    assert res["solve"]["converged"] and res["solve"]["iterations"] == 0
+    assert host_rrn(s.A, s.b, x) <= 1e-3
+
+
+def test_edge_cases():
+    s = synth.plain_2d(N=16, seed=1)
+    # b = 0: x = 0, nothing probed
+    res, x, _ = gpu_auto(s.A, np.zeros(s.A.n), 10, 1e-8, ["frsz2_32", "float32"], 5,
+                         x0=np.ones(s.A.n))
+    assert res["status"] == 0 and res["probed"] == 0 and res["solve"]["converged"]
+    assert not x.any()
+    # x0 already meets tol: nothing probed, x unchanged
+    xs = np.linalg.solve(s.A.scipy().toarray(), s.b)
+    res, x, _ = gpu_auto(s.A, s.b, 10, 1e-8, ["frsz2_32", "float32"], 5, x0=xs)
+    assert res["status"] == 0 and res["probed"] == 0 and res["solve"]["iterations"] == 0
+    assert np.array_equal(x, xs) and res["rel_residual0"] <= 1e-8
+    # a caller workspace of the stated size gives the same result bit for bit
+    r1, x1, _ = gpu_auto(s.A, s.b, 12, 1e-9, ["frsz2_21"], 4)
+    r2, x2, _ = gpu_auto(s.A, s.b, 12, 1e-9, ["frsz2_21"], 4, workspace=True)
+    assert r1["solve"]["iterations"] == r2["solve"]["iterations"]
+    assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+    # probe longer than the restart length; n = 1
+    r3, x3, _ = gpu_auto(s.A, s.b, 3, 1e-9, ["float32", "frsz2_16"], 50)
+    assert r3["solve"]["converged"] and host_rrn(s.A, s.b, x3) <= 1e-9 * (1 + 1e-6)
+    one = synth.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    r4, x4, _ = gpu_auto(one, np.array([2.0]), 5, 1e-12, ["frsz2_32", "float16"], 3)
+    assert r4["solve"]["converged"] and x4[0] == pytest.approx(0.5, rel=1e-15)
+
+
+def test_full_size_sweep_system():
+    """The n = 10^6 convection-diffusion system, GMRES(100) to 1e-10, three
+    candidates probed for 20 steps: properties that hold at any size."""
+    s = synth.sweep_3d(N=100, seed=1)
+    cands = ["frsz2_32", "float32", "float16"]
+    res, x, _ = gpu_auto(s.A, s.b, 100, 1e-10, cands, 20)
+    res["cands"], res["tol"] = cands, 1e-10
+    print({k: res[k] for k in ("chosen", "probe_steps", "probe_rel_residual", "probe_seconds", "seconds")},
+          res["solve"]["iterations"])
+    assert res["status"] == 0 and res["probed"] == 3 and res["solve"]["converged"]
+    check_choice(res)
+    assert all(p == 20 for p in res["probe_steps"])
+    assert all(r < res["rel_residual0"] for r in res["probe_rel_residual"])
+    assert host_rrn(s.A, s.b, x) <= 1e-10 * (1 + 1e-6)
+    err = np.linalg.norm(x - s.x_star) / np.linalg.norm(s.x_star)
+    assert err < 1e-5
