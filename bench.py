@@ -24,7 +24,8 @@ the continuous-batching server (p50/p99 latency, solves/s); `precision` runs
 FP64 iterative refinement around a frsz2_16-basis GMRES(100) against the
 float64-basis solve on the 2^22-row banded system; `intensity` the
 arithmetic-intensity sweep; `adaptive` the solve with its basis format picked
-by probing candidates before the first restart, against every fixed format.
+by probing candidates before the first restart, against every fixed format;
+`precond` Jacobi right preconditioning on the column-scaled sweep operator.
 
 Prints one JSON line.
 """
@@ -346,6 +347,53 @@ def adaptive_bench(cb, torch, grid, steps, warmup, probe_steps):
     return out, s
 
 
+def precond_bench(cb, torch, grid, steps, warmup):
+    """Jacobi right preconditioning on the sweep operator with its columns
+    scaled by 10^U(-3,3) (seed 6): the preconditioned solve per basis format,
+    the unpreconditioned one capped at 2000 steps, and the unscaled system's
+    plain solve for reference."""
+    import synth
+    base = synth.sweep_3d(N=grid, seed=1)
+    s = synth.column_scaled(base, decades=3.0)
+    A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    b = torch.from_numpy(s.b).cuda()
+    x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    m, tol = 100, 1e-10
+    out = {}
+
+    def run(fn):
+        r = None
+        for _ in range(warmup):
+            x.zero_()
+            r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    t_setup, d = run(lambda: cb.cb_jacobi_setup(A))
+    out["jacobi_setup_s"] = t_setup
+    for fmt in ("frsz2_32", "float64", "frsz2_16", "float32"):
+        tt, r = run(lambda: cb.cbgmres_solve(A, b, x, m, tol, fmt, diag_inv=d)[0])
+        rrn = float(np.linalg.norm(s.b - s.A.scipy() @ x.cpu().numpy()) / np.linalg.norm(s.b))
+        out[f"jacobi_{fmt}"] = {"seconds": tt, "iterations": r["iterations"], "converged": bool(r["converged"]),
+                                "rel_residual": rrn}
+        log(f"precond: jacobi {fmt}: {tt * 1e3:.1f} ms, {r['iterations']} iterations, rrn {rrn:.2e}")
+    tt, r = run(lambda: cb.cbgmres_solve(A, b, x, m, tol, "frsz2_32", max_iters=2000)[0])
+    out["none_frsz2_32_capped_2000"] = {"seconds": tt, "iterations": r["iterations"],
+                                        "converged": bool(r["converged"]), "rel_residual": r["rel_residual"]}
+    log(f"precond: none frsz2_32: {tt * 1e3:.1f} ms, {r['iterations']} iterations, rel {r['rel_residual']:.2e}")
+    Ab = cb.DeviceCSR.from_host(base.A.row_ptr, base.A.col, base.A.val)
+    bb = torch.from_numpy(base.b).cuda()
+    tt, r = run(lambda: cb.cbgmres_solve(Ab, bb, x, m, tol, "frsz2_32")[0])
+    out["unscaled_plain_frsz2_32"] = {"seconds": tt, "iterations": r["iterations"]}
+    log(f"precond: unscaled plain frsz2_32: {tt * 1e3:.1f} ms, {r['iterations']} iterations")
+    return out, s
+
+
 SWEEP_OPS = (0, 1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 112, 128, 160,
              192, 256)
 
@@ -404,12 +452,13 @@ def main():
                     help="also copy 1 GiB once: the reference kernel for FETCH/WRITE_SIZE")
     ap.add_argument("--probe-steps", type=int, default=20, help="probe length of the adaptive workload")
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "serving", "precision", "intensity", "adaptive"],
+                    choices=["sweep", "serving", "precision", "intensity", "adaptive", "precond"],
                     help="sweep: the n=1e6 solve + kernel microbench (default); serving: the "
                          "request stream through the continuous-batching server; precision: FP64 "
                          "iterative refinement around a frsz2_16-basis GMRES at n=2^22; intensity: the "
                          "arithmetic-intensity sweep over 2^28 values per format; adaptive: the basis "
-                         "format picked by probing against every fixed format")
+                         "format picked by probing against every fixed format; precond: Jacobi right "
+                         "preconditioning on the column-scaled sweep operator")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -477,6 +526,18 @@ def main():
                                       f"x0=0; candidates {','.join(av['candidates'])}, "
                                       f"{args.probe_steps}-step probes"},
                "adaptive": av}
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "precond":
+        pv, s = precond_bench(cb, torch, args.grid, args.steps, args.warmup)
+        rec = {"metric": "time-to-1e-10 residual, Jacobi right-preconditioned GMRES(100), frsz2_32 basis",
+               "value": pv["jacobi_frsz2_32"]["seconds"], "unit": "s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": pv["jacobi_frsz2_32"]["seconds"] * 1e3,
+               "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic",
+               "config": {"workload": f"cd3d N={args.grid} (n={s.A.n}, nnz={s.A.nnz}) with columns scaled by "
+                                      "10^U(-3,3) (seed 6), GMRES(100), tol 1e-10, x0=0"},
+               "precond": pv}
         print(json.dumps(rec), flush=True)
         return
     m, tol = 100, 1e-10

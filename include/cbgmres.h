@@ -230,6 +230,44 @@ int cbgmres_solve(const cb_csr* A, const double* b, double* x, int32_t m, double
                   const cb_options* opt, void* workspace, size_t workspace_bytes,
                   double* history_host, int64_t history_cap, cb_result* result_host, void* stream);
 
+/* ======================================================================
+ * Preconditioned solve (Fig. 1 with M != I): right preconditioning, so the
+ * Arnoldi steps build the Krylov space of A M^-1 (step 3: w = A (M^-1 v))
+ * and the update is x = x0 + M^-1 (V y) (step 17); the stop test stays on
+ * ||b - A x||.  The preconditioner offered is Jacobi, M = diag(A).
+ * ====================================================================== */
+typedef enum cb_precond_kind {
+    CB_PRECOND_NONE = 0,
+    CB_PRECOND_JACOBI = 1
+} cb_precond_kind;
+
+typedef struct cb_precond {
+    int32_t kind;             /* cb_precond_kind */
+    int32_t reserved;         /* 0 */
+    const double* diag_inv;   /* JACOBI: device float64[n], M^-1 = diag(diag_inv) */
+} cb_precond;
+
+/* diag_inv[i] = 1 / a_ii by IEEE division (device float64[n], caller-owned);
+ * 1 where row i has no diagonal entry or it is zero or not finite.
+ * Asynchronous. */
+int cb_jacobi_setup(const cb_csr* A, double* diag_inv, void* stream);
+
+/* Device workspace bytes cbgmres_solve_precond needs: the solver workspace
+ * plus nnz float64 values of A M^-1. */
+int64_t cbgmres_precond_workspace_bytes(int32_t n, int32_t nnz, int32_t m, int format);
+
+/* As cbgmres_solve, with the right preconditioner M (NULL or kind NONE: the
+ * plain solve, workspace as for cbgmres_solve).  For JACOBI the values of
+ * A M^-1 (a_ij * diag_inv[j], one rounding per entry) are formed in the
+ * workspace once per call and the Arnoldi SpMV reads them, so a step costs
+ * what an unpreconditioned step costs; the update x += M^-1 (V y) sums each
+ * row's correction first, then scales it.  Synchronous.  CB_ERR_INVALID_ARG
+ * for an unknown kind or a NULL diag_inv. */
+int cbgmres_solve_precond(const cb_csr* A, const double* b, double* x, int32_t m, double tol, int format,
+                          const cb_precond* M, const cb_options* opt, void* workspace,
+                          size_t workspace_bytes, double* history_host, int64_t history_cap,
+                          cb_result* result_host, void* stream);
+
 /* Mixed-precision form: FP64 iterative refinement around an inner
  * compressed-basis GMRES.  Each outer step computes r = b - A x in FP64,
  * runs one inner cycle of GMRES(m) on A d = r from d = 0 with the given basis

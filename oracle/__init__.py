@@ -62,6 +62,8 @@ def lib():
             "or_gmres_cycle": (None, [i64, P, P, P, P, d, i32, i32, d, i32, d, i32, P, P, P, P,
                                       P, P, P, P]),
             "or_ir_solve": (i32, [i64, P, P, P, P, P, i32, d, d, i32, i32, P]),
+            "or_gmres_pc": (i32, [i64, P, P, P, P, P, P, i32, d, i32, P, P, P, i64]),
+            "or_jacobi_diag_inv": (None, [i64, P, P, P, P]),
             "or_dense_solve": (i32, [i32, P, P]),
             "or_rounding_is_nearest": (i32, []),
         }
@@ -258,17 +260,27 @@ class GmresResult:
 
 def gmres(A, b, m: int, tol: float, fmt="float64", x0=None, eta: float = 0.7071067811865476,
           max_iters: int = 20000, max_cycles: int = 0, literal_breakdown: bool = False,
-          hist_cap: int = 0) -> GmresResult:
+          hist_cap: int = 0, dinv=None) -> GmresResult:
+    """Restarted GMRES(m); dinv (optional) is the Jacobi right preconditioner
+    M^-1 = diag(dinv) of Fig. 1 steps 3 and 17."""
     b = np.ascontiguousarray(b, np.float64)
     x = np.zeros(A.n, np.float64) if x0 is None else np.array(x0, np.float64, copy=True)
     st = _Stats()
     opt = _Options(eta, max_iters, max_cycles, int(literal_breakdown))
     hist = np.zeros(max(hist_cap, 1), np.float64)
-    lib().or_gmres(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), _p(x), m, tol, _fmt(fmt),
-                   C.byref(opt), C.byref(st), _p(hist), hist_cap)
+    dv = None if dinv is None else np.ascontiguousarray(dinv, np.float64)
+    lib().or_gmres_pc(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), None if dv is None else _p(dv), _p(b),
+                      _p(x), m, tol, _fmt(fmt), C.byref(opt), C.byref(st), _p(hist), hist_cap)
     return GmresResult(x, st.iterations, st.restarts, st.reorths, st.breakdowns,
                        bool(st.converged), st.status, st.rel_residual,
                        st.implicit_rel_residual, hist[:min(hist_cap, st.iterations)])
+
+
+def jacobi(A) -> np.ndarray:
+    """dinv[i] = 1 / a_ii (1 where the diagonal is missing, zero or not finite)."""
+    out = np.empty(A.n, np.float64)
+    lib().or_jacobi_diag_inv(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(out))
+    return out
 
 
 @dataclass

@@ -374,11 +374,11 @@ typedef struct {
  *   hist      nullable; |g_{j+1}| per step
  * Stops after m steps, when |g_{j+1}| <= tol_abs, on breakdown, or after
  * max_steps steps. */
-void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-                    const double* r, double beta, int m, int fmt, double eta, int literal,
-                    double tol_abs, int max_steps, unsigned char* enc, uint32_t* exps,
-                    double* Vdec, double* H, double* Hraw, double* y, double* hist,
-                    or_cycle_info* info) {
+static void gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                        const double* dinv, const double* r, double beta, int m, int fmt, double eta,
+                        int literal, double tol_abs, int max_steps, unsigned char* enc, uint32_t* exps,
+                        double* Vdec, double* H, double* Hraw, double* y, double* hist,
+                        or_cycle_info* info) {
     int64_t cb = or_basis_col_bytes(fmt, n);
     int64_t nbk = nblocks_of(n);
     double* cs = malloc((size_t)m * 8);
@@ -387,6 +387,7 @@ void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const
     double* w = malloc((size_t)n * 8);
     double* v = malloc((size_t)n * 8);
     double* u = malloc((size_t)(m + 1) * 8);
+    double* z = dinv ? malloc((size_t)n * 8) : NULL;
     memset(info, 0, sizeof *info);
     memset(H, 0, (size_t)(m + 1) * m * 8);
     if (Hraw) memset(Hraw, 0, (size_t)(m + 1) * m * 8);
@@ -398,8 +399,14 @@ void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const
     g[0] = beta;
     for (int j = 0; j < m; ++j) {
         double* h = H + (int64_t)j * (m + 1);
-        /* Steps 3-4: w = A v with the FP64 v, omega = ||w|| */
-        or_spmv(n, row_ptr, col, val, v, w);
+        /* Steps 3-4: w = A (M^-1 v) with the FP64 v, omega = ||w||; with a
+         * Jacobi preconditioner M^-1 v is the entrywise product dinv * v */
+        if (dinv) {
+            for (int64_t k = 0; k < n; ++k) z[k] = dinv[k] * v[k];
+            or_spmv(n, row_ptr, col, val, z, w);
+        } else {
+            or_spmv(n, row_ptr, col, val, v, w);
+        }
         double omega = or_nrm2(n, w);
         /* Steps 5-6: classical Gram-Schmidt against the stored basis */
         or_cgs_project(n, j + 1, Vdec, n, w, h);
@@ -452,14 +459,38 @@ void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const
         y[i] = s / H[(int64_t)i * (m + 1) + i];
     }
 done:
-    free(cs); free(sn); free(g); free(w); free(v); free(u);
+    free(cs); free(sn); free(g); free(w); free(v); free(u); free(z);
+}
+
+void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                    const double* r, double beta, int m, int fmt, double eta, int literal,
+                    double tol_abs, int max_steps, unsigned char* enc, uint32_t* exps,
+                    double* Vdec, double* H, double* Hraw, double* y, double* hist,
+                    or_cycle_info* info) {
+    gmres_cycle(n, row_ptr, col, val, NULL, r, beta, m, fmt, eta, literal, tol_abs, max_steps, enc,
+                exps, Vdec, H, Hraw, y, hist, info);
+}
+
+/* Jacobi preconditioner M = diag(A) (Fig. 1's M, the simplest choice):
+ * dinv[i] = 1 / a_ii by IEEE division; a row whose diagonal entry is missing,
+ * zero or not finite keeps dinv[i] = 1 (left unscaled). */
+void or_jacobi_diag_inv(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                        double* dinv) {
+    for (int64_t i = 0; i < n; ++i) {
+        dinv[i] = 1.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i && val[k] != 0.0 && isfinite(val[k])) dinv[i] = 1.0 / val[k];
+    }
 }
 
 /* Restarted GMRES(m): cycles from the current x until the explicit relative
- * residual (Eq. 4) meets tol.  x holds x0 on entry and the iterate on return. */
-int or_gmres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
-             const double* b, double* x, int m, double tol, int fmt, const or_options* opt,
-             or_stats* st, double* hist, int64_t hist_cap) {
+ * residual (Eq. 4) meets tol.  x holds x0 on entry and the iterate on return.
+ * dinv (nullable) is the right preconditioner M^-1 = diag(dinv), Fig. 1 steps
+ * 3 and 17: the Krylov space is that of A M^-1 and the update is
+ * x = x0 + M^-1 (V y); the explicit residual stays b - A x. */
+int or_gmres_pc(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+                const double* dinv, const double* b, double* x, int m, double tol, int fmt,
+                const or_options* opt, or_stats* st, double* hist, int64_t hist_cap) {
     double eta = opt ? opt->eta : 0.7071067811865476;
     int max_iters = (opt && opt->max_iters > 0) ? opt->max_iters : 20000;
     int max_cycles = opt ? opt->max_cycles : 0;
@@ -495,8 +526,8 @@ int or_gmres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double
         if (st->iterations >= max_iters) { status = 3; break; }
         st->restarts += 1;
         or_cycle_info ci;
-        or_gmres_cycle(n, row_ptr, col, val, r, beta, m, fmt, eta, literal, tol * nb,
-                       max_iters - st->iterations, enc, exps, Vdec, H, NULL, y, ch, &ci);
+        gmres_cycle(n, row_ptr, col, val, dinv, r, beta, m, fmt, eta, literal, tol * nb,
+                    max_iters - st->iterations, enc, exps, Vdec, H, NULL, y, ch, &ci);
         for (int j = 0; j < ci.steps; ++j) {
             if (hist && st->iterations + j < hist_cap) hist[st->iterations + j] = ch[j] / nb;
         }
@@ -505,11 +536,11 @@ int or_gmres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double
         st->breakdowns += ci.breakdown;
         if (ci.steps > 0) st->implicit_rel_residual = ci.gabs / nb;
         if (ci.status) { status = ci.status; break; }
-        /* Step 17: x = x0 + V y, each row's correction summed first */
+        /* Step 17: x = x0 + M^-1 (V y), each row's correction summed first */
         for (int64_t k = 0; k < n; ++k) {
             double s = 0.0;
             for (int i = 0; i < ci.steps; ++i) s += y[i] * Vdec[(int64_t)i * n + k];
-            x[k] = x[k] + s;
+            x[k] = x[k] + (dinv ? dinv[k] * s : s);
         }
         if (max_cycles > 0 && st->restarts >= max_cycles) {
             status = 3;
@@ -520,6 +551,12 @@ int or_gmres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double
     st->status = status;
     free(enc); free(exps); free(Vdec); free(H); free(y); free(r); free(ch);
     return status;
+}
+
+int or_gmres(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
+             const double* b, double* x, int m, double tol, int fmt, const or_options* opt,
+             or_stats* st, double* hist, int64_t hist_cap) {
+    return or_gmres_pc(n, row_ptr, col, val, NULL, b, x, m, tol, fmt, opt, st, hist, hist_cap);
 }
 
 /* ------------------------------------------------------------------------ */

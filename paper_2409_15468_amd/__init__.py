@@ -56,6 +56,13 @@ class cb_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+CB_PRECOND_NONE, CB_PRECOND_JACOBI = 0, 1
+
+
+class cb_precond(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("diag_inv", C.c_void_p)]
+
+
 CB_AUTO_MAX_CANDIDATES = 8
 
 
@@ -107,6 +114,10 @@ SIGNATURES = {
                                 _P, _SZ, _P, _I64, C.POINTER(cb_result), _P]),
     "cbgmres_ir_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _D, C.c_int, _I32,
                                    C.POINTER(cb_result), _P]),
+    "cb_jacobi_setup": (C.c_int, [C.POINTER(cb_csr), _P, _P]),
+    "cbgmres_precond_workspace_bytes": (_I64, [_I32, _I32, _I32, C.c_int]),
+    "cbgmres_solve_precond": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, C.c_int, C.POINTER(cb_precond),
+                                        C.POINTER(cb_options), _P, _SZ, _P, _I64, C.POINTER(cb_result), _P]),
     "cb_auto_pick": (_I32, [_D, _P, _P, _I32]),
     "cbgmres_auto_workspace_bytes": (_I64, [_I32, _I32, _I32, _P, _I32]),
     "cbgmres_solve_auto": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _P, _I32, _I32,
@@ -404,14 +415,29 @@ def cbgmres_workspace_bytes(n: int, m: int, fmt) -> int:
     return int(lib().cbgmres_workspace_bytes(n, m, _fmt(fmt)))
 
 
+def cb_jacobi_setup(A: DeviceCSR, stream=None):
+    """The Jacobi preconditioner's diag_inv (device float64[n]): 1 / a_ii."""
+    import torch
+    d = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    desc = A.desc()
+    _check(lib().cb_jacobi_setup(C.byref(desc), _ptr(d), _stream(stream)), "cb_jacobi_setup")
+    return d
+
+
+def cbgmres_precond_workspace_bytes(n: int, nnz: int, m: int, fmt) -> int:
+    return int(lib().cbgmres_precond_workspace_bytes(n, nnz, m, _fmt(fmt)))
+
+
 def cbgmres_solve(A: DeviceCSR, b, x, m: int, tol: float, fmt="frsz2_32", eta: float = 0.0,
                   max_iters: int = 0, max_cycles: int = 0, literal_breakdown: bool = False,
                   workspace=None, history_cap: int = 0, stream=None, check: bool = True,
-                  fuse_updates: int = 0):
+                  fuse_updates: int = 0, diag_inv=None):
     """Solve A x = b in place on x (x holds x0).  Returns (result dict,
     history numpy array of implicit relative residuals).  Solver outcomes
     (converged, not converged, non-finite) come back in result["status"];
-    argument and runtime errors raise CbError."""
+    argument and runtime errors raise CbError.  diag_inv (device float64[n],
+    e.g. from cb_jacobi_setup) selects the Jacobi right preconditioner
+    M^-1 = diag(diag_inv) (cbgmres_solve_precond)."""
     import numpy as np
     import torch
     _dev(x, torch.float64, "x")
@@ -423,9 +449,19 @@ def cbgmres_solve(A: DeviceCSR, b, x, m: int, tol: float, fmt="frsz2_32", eta: f
     hist = np.zeros(max(history_cap, 1), np.float64)
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     d = A.desc()
-    st = lib().cbgmres_solve(C.byref(d), _ptr(b), _ptr(x), m, tol, _fmt(fmt), C.byref(opt),
-                             _ptr(workspace), nbytes, hist.ctypes.data_as(C.c_void_p), history_cap,
-                             C.byref(res), _stream(stream))
+    if diag_inv is None:
+        st = lib().cbgmres_solve(C.byref(d), _ptr(b), _ptr(x), m, tol, _fmt(fmt), C.byref(opt),
+                                 _ptr(workspace), nbytes, hist.ctypes.data_as(C.c_void_p), history_cap,
+                                 C.byref(res), _stream(stream))
+    else:
+        _dev(diag_inv, torch.float64, "diag_inv")
+        if diag_inv.numel() != A.n:
+            raise ValueError("diag_inv must have n entries")
+        M = cb_precond(CB_PRECOND_JACOBI, 0, diag_inv.data_ptr())
+        st = lib().cbgmres_solve_precond(C.byref(d), _ptr(b), _ptr(x), m, tol, _fmt(fmt), C.byref(M),
+                                         C.byref(opt), _ptr(workspace), nbytes,
+                                         hist.ctypes.data_as(C.c_void_p), history_cap, C.byref(res),
+                                         _stream(stream))
     if check and st not in (CB_OK, CB_ERR_NOT_CONVERGED, CB_ERR_NONFINITE):
         _check(st, "cbgmres_solve")
     out = res.as_dict()

@@ -176,6 +176,35 @@ __global__ void k_axpy(double* __restrict__ x, const double* __restrict__ d, int
     if (i < n) x[i] = x[i] + d[i];
 }
 
+// x += M^-1 t for the Jacobi preconditioner, one product and one sum per entry
+// (no contraction, as the step is written).
+__global__ void k_precond_update(double* __restrict__ x, const double* __restrict__ dinv,
+                                 const double* __restrict__ t, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = __dadd_rn(x[i], __dmul_rn(dinv[i], t[i]));
+}
+
+// dinv[i] = 1 / a_ii (IEEE division); 1 where the row has no diagonal entry or
+// it is zero or not finite.  One thread per row.
+__global__ void k_jacobi(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                         const double* __restrict__ val, int n, double* __restrict__ dinv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double d = 1.0;
+    for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        const double a = val[k];
+        if (col[k] == i && a != 0.0 && isfinite(a)) d = 1.0 / a;
+    }
+    dinv[i] = d;
+}
+
+// The values of A M^-1: column j of A scaled by dinv[j], one product per entry.
+__global__ void k_scale_cols(const int32_t* __restrict__ col, const double* __restrict__ val,
+                             const double* __restrict__ dinv, int64_t nnz, double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) out[k] = __dmul_rn(val[k], dinv[col[k]]);
+}
+
 // ----------------------------------------------------------------- host side
 struct Pinned {
     void* p = nullptr;
@@ -212,9 +241,14 @@ static void enqueue_sumsq(const double* x, int n, double* part, double* dst, hip
 }
 
 // The solve proper, on a prepared workspace.  Returns a cb_status.
+// With a Jacobi right preconditioner (dinv non-NULL) the Arnoldi SpMV runs on
+// A M^-1, whose values pval (A's values with column j scaled by dinv[j]) the
+// caller has formed, and the x update adds M^-1 (V y); the explicit residual
+// stays b - A x.
 static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double tol, int fmt,
                       const cb_options* opt, const Ws& W, double* history_host,
-                      int64_t history_cap, cb_result* res, hipStream_t s) {
+                      int64_t history_cap, cb_result* res, hipStream_t s,
+                      const double* dinv = nullptr, const double* pval = nullptr) {
     const double t0 = now_s();
     const int n = A.n;
     const double eta = (opt && opt->eta > 0) ? opt->eta : 0.7071067811865476;
@@ -238,6 +272,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     double* part = W.at<double>(W.L.part);
     double* part_s = W.at<double>(W.L.part_s);
     const int Gs = spmv_groups(n, A.nnz);
+    cb_csr AM = A;  // the operator of the Arnoldi steps: A, or A M^-1
+    if (dinv) AM.val = pval;
     cb_basis V{fmt, n, m + 1, 0, W.base + W.L.vals,
                frsz2_bits_of(fmt) ? W.at<uint32_t>(W.L.exps) : nullptr};
     const double cbytes = (double)column_bytes(fmt, n);
@@ -312,7 +348,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 double* hcol = H + (int64_t)j * (m + 1);
                 // v_j = w / (beta or h_{j,j-1}), V_j = Q(v_j), w = A v_j; its
                 // ||w||^2 partials go to the first update's epilogue
-                launch_spmv_store(fmt, A, V, j, wc, j == 0 ? &st->beta : &st->hn, wn, part_s, flag, active, s);
+                launch_spmv_store(fmt, AM, V, j, wc, j == 0 ? &st->beta : &st->hn, wn, part_s, flag, active, s);
                 double* t = wc;
                 wc = wn;
                 wn = t;
@@ -345,7 +381,15 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 launch_subtract(fmt, V, j + 1, nullptr, u, wc, part, reorth, -1, ef, s);
             }
             k_backsolve<<<1, 256, 0, s>>>(st, H, g, y, m, cbytes);
-            launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, Epi{}, s);
+            if (dinv) {
+                // t = V y into the free w2 (from zero, so t is the row sums
+                // exactly), then x += M^-1 t
+                launch_fill(w2, 0.0, n, s);
+                launch_subtract(fmt, V, m, steps, y, w2, nullptr, steps, +1, Epi{}, s);
+                k_precond_update<<<(n + 255) / 256, 256, 0, s>>>(x, dinv, w2, n);
+            } else {
+                launch_subtract(fmt, V, m, steps, y, x, nullptr, steps, +1, Epi{}, s);
+            }
             CB_HIP(hipGetLastError());
             ++cycles;
             if (max_cycles > 0 && cycles >= max_cycles) {
@@ -428,6 +472,58 @@ int cbgmres_solve(const cb_csr* A, const double* b, double* x, int32_t m, double
     if (owned) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(W.base);
+    }
+    return st;
+}
+
+int cb_jacobi_setup(const cb_csr* A, double* diag_inv, void* stream) {
+    if (!A || !diag_inv || A->n < 1 || !A->row_ptr || A->nnz < 0 || (A->nnz && (!A->col || !A->val)))
+        return fail(CB_ERR_INVALID_ARG, "bad matrix or output");
+    k_jacobi<<<(A->n + 255) / 256, 256, 0, (hipStream_t)stream>>>(A->row_ptr, A->col, A->val, A->n, diag_inv);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int64_t cbgmres_precond_workspace_bytes(int32_t n, int32_t nnz, int32_t m, int format) {
+    if (n < 1 || nnz < 0 || m < 1 || !valid_format(format)) return -1;
+    return layout_of(n, m, format).total + al((int64_t)nnz * 8);
+}
+
+int cbgmres_solve_precond(const cb_csr* A, const double* b, double* x, int32_t m, double tol, int format,
+                          const cb_precond* M, const cb_options* opt, void* workspace,
+                          size_t workspace_bytes, double* history_host, int64_t history_cap,
+                          cb_result* result_host, void* stream) {
+    if (!M || M->kind == CB_PRECOND_NONE)
+        return cbgmres_solve(A, b, x, m, tol, format, opt, workspace, workspace_bytes, history_host,
+                             history_cap, result_host, stream);
+    if (M->kind != CB_PRECOND_JACOBI || !M->diag_inv)
+        return fail(CB_ERR_INVALID_ARG, "unknown preconditioner kind %d or NULL diag_inv", M->kind);
+    if (int e = check_solve_args(A, b, x, m, tol, format)) return e;
+    const int64_t total = cbgmres_precond_workspace_bytes(A->n, A->nnz, m, format);
+    if (workspace && (int64_t)workspace_bytes < total)
+        return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", workspace_bytes, (long long)total);
+    hipStream_t s = (hipStream_t)stream;
+    Ws W;
+    W.L = layout_of(A->n, m, format);
+    void* owned = nullptr;
+    if (workspace) {
+        W.base = static_cast<unsigned char*>(workspace);
+    } else {
+        CB_HIP(hipMalloc(&owned, (size_t)total));
+        W.base = static_cast<unsigned char*>(owned);
+    }
+    double* pval = reinterpret_cast<double*>(W.base + W.L.total);
+    if (A->nnz)
+        k_scale_cols<<<(unsigned)((A->nnz + 255) / 256), 256, 0, s>>>(A->col, A->val, M->diag_inv, A->nnz, pval);
+    int st = CB_OK;
+    if (hipGetLastError() != hipSuccess)
+        st = fail(CB_ERR_HIP, "launch failed");
+    else
+        st = solve_impl(*A, b, x, m, tol, format, opt, W, history_host, history_cap, result_host, s,
+                        M->diag_inv, pval);
+    if (owned) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(owned);
     }
     return st;
 }

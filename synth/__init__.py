@@ -117,6 +117,19 @@ def sweep_3d(N: int = 100, seed: int = 1) -> LinearSystem:
     return LinearSystem(A, rhs_from_solution(A, x), x, f"cd3d_N{N}")
 
 
+def column_scaled(base: LinearSystem, decades: float = 3.0, seed: int = 6) -> LinearSystem:
+    """The system of `base` with column j of A multiplied by 10^u_j,
+    u ~ U(-decades, decades) from default_rng(seed): A' = A S, x*' = S^-1 x*,
+    b unchanged.  Badly scaled unknowns, as a diagonal (Jacobi) preconditioner
+    is meant to fix."""
+    A = base.A
+    s = 10.0 ** np.random.default_rng(seed).uniform(-decades, decades, A.n)
+    val = np.ascontiguousarray(A.val * s[A.col], dtype=np.float64)
+    As = CSR(A.n, A.row_ptr.copy(), A.col.copy(), val)
+    xs = base.x_star / s
+    return LinearSystem(As, rhs_from_solution(As, xs), xs, base.name + f"_colscaled{decades:g}")
+
+
 def banded_random(n: int = 1 << 22, per_row: int = 27, half_band: int = 1000,
                   diag_factor: float = 1.2, seed: int = 3) -> LinearSystem:
     """Random nonsymmetric banded matrix: the diagonal plus per_row-1 distinct

@@ -140,3 +140,26 @@ def test_auto_solve_arguments_without_device_work():
     assert call([5, 2], 10, m=0) == cb.CB_ERR_INVALID_ARG
     assert call([5, 2], 10, tol=0.0) == cb.CB_ERR_INVALID_ARG
     assert call([5, 2], 10, ws_bytes=need - 1) == cb.CB_ERR_WORKSPACE
+
+
+def test_precond_arguments_without_device_work():
+    """cbgmres_solve_precond and cb_jacobi_setup reject bad arguments before
+    any device work.  Pointers here are never dereferenced."""
+    L = cb.lib()
+    res = cb.cb_result()
+    A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    need = cb.cbgmres_precond_workspace_bytes(1000, 5000, 30, "frsz2_16")
+    assert need >= cb.cbgmres_workspace_bytes(1000, 30, "frsz2_16") + 8 * 5000
+    assert cb.cbgmres_precond_workspace_bytes(0, 5000, 30, "frsz2_16") == -1
+    assert cb.cbgmres_precond_workspace_bytes(1000, 5000, 30, 9) == -1
+
+    def call(kind, diag, ws_bytes=need, m=30):
+        M = cb.cb_precond(kind, 0, diag)
+        return L.cbgmres_solve_precond(C.byref(A), 256, 256, m, 1e-8, 3, C.byref(M), None, 256, ws_bytes,
+                                       None, 0, C.byref(res), None)
+    assert call(7, 256) == cb.CB_ERR_INVALID_ARG
+    assert call(cb.CB_PRECOND_JACOBI, None) == cb.CB_ERR_INVALID_ARG
+    assert call(cb.CB_PRECOND_JACOBI, 256, m=513) == cb.CB_ERR_INVALID_ARG
+    assert call(cb.CB_PRECOND_JACOBI, 256, ws_bytes=need - 1) == cb.CB_ERR_WORKSPACE
+    assert L.cb_jacobi_setup(None, 256, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_jacobi_setup(C.byref(cb.cb_csr(0, 0, 256, None, None)), 256, None) == cb.CB_ERR_INVALID_ARG
