@@ -37,7 +37,7 @@ extern "C" {
 typedef enum cb_status {
     CB_OK = 0,
     CB_ERR_INVALID_ARG = 1,      /* null pointer, bad size, bad format ... */
-    CB_ERR_UNSUPPORTED_BITS = 2, /* FRSZ2 bit width other than 16, 21, 32 */
+    CB_ERR_UNSUPPORTED_BITS = 2, /* FRSZ2 bit width outside 3..32 */
     CB_ERR_NONFINITE = 3,        /* Inf/NaN met in a solve */
     CB_ERR_NOT_CONVERGED = 4,    /* iteration or cycle cap reached */
     CB_ERR_WORKSPACE = 5,        /* workspace too small */
@@ -58,6 +58,16 @@ typedef enum cb_basis_format {
     CB_FRSZ2_21 = 4,
     CB_FRSZ2_32 = 5
 } cb_basis_format;
+
+/* FRSZ2 with any l in [3, 32] (l is a free parameter of the format, Section
+ * IV-A): format number CB_FRSZ2_BITS(l), run by a generic codec whose lanes
+ * walk their codes with a runtime bit offset.  The storage layout and the
+ * codes are those of the fixed formats: CB_FRSZ2_BITS(16), (21) and (32)
+ * store the same bits as CB_FRSZ2_16, _21 and _32, which have specialised
+ * (faster) kernels.  Every entry point that takes a format accepts these,
+ * except the batched small-system solver. */
+#define CB_FRSZ2_GENERIC_BASE 64
+#define CB_FRSZ2_BITS(l) (CB_FRSZ2_GENERIC_BASE + (l))
 
 const char* cb_status_string(int status);
 const char* cb_last_error(void);
@@ -80,10 +90,11 @@ const char* cb_last_error(void);
 
 /* ceil(n/32) */
 int64_t frsz2_exponent_words(int64_t n);
-/* bits * ceil(n/32), or -1 for an unsupported width */
+/* bits * ceil(n/32), or -1 for a width outside 3..32 */
 int64_t frsz2_value_words(int64_t n, int bits);
 
-/* Compress x[n] (float64) into exps/words.  bits in {16, 21, 32}.
+/* Compress x[n] (float64) into exps/words.  3 <= bits <= 32 (16, 21 and 32
+ * use the specialised kernels).
  * nonfinite_flag (nullable, device int32) is set to 1 -- never cleared -- when
  * a block holds Inf or NaN; that block's words are then unspecified.
  * Asynchronous. */

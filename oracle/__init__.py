@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FORMATS = {"float64": 0, "float32": 1, "float16": 2, "frsz2_16": 3, "frsz2_21": 4, "frsz2_32": 5}
-FRSZ2_BITS = {3: 16, 4: 21, 5: 32}
+FRSZ2_BITS = {3: 16, 4: 21, 5: 32, **{64 + l: l for l in range(3, 33)}}
 
 
 def build() -> str:
@@ -79,8 +79,23 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def frsz2_any(l: int) -> int:
+    """Format number of FRSZ2 with l bits, 3 <= l <= 32 (64 + l)."""
+    if not 3 <= l <= 32:
+        raise ValueError("l must lie in [3, 32]")
+    return 64 + l
+
+
 def _fmt(fmt) -> int:
-    return FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    """A format name or number: the six names above, "frsz2_<l>" for any other
+    l in [3, 32], "frsz2g_<l>" for the number 64 + l of any l."""
+    if not isinstance(fmt, str):
+        return int(fmt)
+    if fmt in FORMATS:
+        return FORMATS[fmt]
+    if fmt.startswith("frsz2_") or fmt.startswith("frsz2g_"):
+        return frsz2_any(int(fmt.split("_")[1]))
+    raise KeyError(fmt)
 
 
 def nblocks(n: int) -> int:

@@ -217,7 +217,12 @@ double or_f64_from_f16(uint16_t h) {
 /* hold +0.0.                                                                */
 /* ------------------------------------------------------------------------ */
 
+/* FRSZ2 with any l in [3, 32]: format number 64 + l (l is a free parameter of
+ * the format, Section IV-A; 16, 21 and 32 also have the numbers above). */
+#define OR_FRSZ2_ANY(l) (64 + (l))
+
 static int frsz2_bits(int fmt) {
+    if (fmt >= OR_FRSZ2_ANY(3) && fmt <= OR_FRSZ2_ANY(32)) return fmt - 64;
     return fmt == OR_FRSZ2_16 ? 16 : fmt == OR_FRSZ2_21 ? 21 : fmt == OR_FRSZ2_32 ? 32 : 0;
 }
 

@@ -165,8 +165,26 @@ def _check(st: int, where: str) -> int:
     return st
 
 
+CB_FRSZ2_GENERIC_BASE = 64
+
+
+def frsz2_bits_format(l: int) -> int:
+    """CB_FRSZ2_BITS(l): FRSZ2 with l bits (3 <= l <= 32) on the generic codec."""
+    if not 3 <= l <= 32:
+        raise ValueError("l must lie in [3, 32]")
+    return CB_FRSZ2_GENERIC_BASE + l
+
+
 def _fmt(fmt) -> int:
-    return FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    """A format name or number: the six names of FORMATS, "frsz2_<l>" for any
+    other l in [3, 32], "frsz2g_<l>" for the generic codec at any l."""
+    if not isinstance(fmt, str):
+        return int(fmt)
+    if fmt in FORMATS:
+        return FORMATS[fmt]
+    if fmt.startswith("frsz2_") or fmt.startswith("frsz2g_"):
+        return frsz2_bits_format(int(fmt.split("_")[1]))
+    raise KeyError(fmt)
 
 
 def _ptr(t):
@@ -266,7 +284,7 @@ class Basis:
 
     def column_data_bytes(self) -> int:
         nb = (self.n + 31) // 32
-        bits = {3: 16, 4: 21, 5: 32}.get(self.fmt)
+        bits = {3: 16, 4: 21, 5: 32}.get(self.fmt, self.fmt - CB_FRSZ2_GENERIC_BASE if self.fmt > 5 else 0)
         return nb * bits * 4 if bits else nb * 32 * (8, 4, 2)[self.fmt]
 
     def column(self, c: int):

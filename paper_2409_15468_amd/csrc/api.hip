@@ -34,7 +34,7 @@ int64_t column_data_bytes(int f, int64_t n) {
     case CB_FRSZ2_16:
     case CB_FRSZ2_21:
     case CB_FRSZ2_32: return nb * frsz2_bits_of(f) * 4;
-    default: return -1;
+    default: return generic_format(f) ? nb * frsz2_bits_of(f) * 4 : -1;
     }
 }
 
@@ -105,18 +105,19 @@ const char* cb_last_error(void) { return g_err; }
 int64_t frsz2_exponent_words(int64_t n) { return n < 0 ? -1 : nblocks(n); }
 
 int64_t frsz2_value_words(int64_t n, int bits) {
-    if (n < 0 || (bits != 16 && bits != 21 && bits != 32)) return -1;
+    if (n < 0 || bits < 3 || bits > 32) return -1;
     return (int64_t)bits * nblocks(n);
 }
 
 static int format_of_bits(int bits) {
-    return bits == 16 ? CB_FRSZ2_16 : bits == 21 ? CB_FRSZ2_21 : bits == 32 ? CB_FRSZ2_32 : -1;
+    return bits == 16 ? CB_FRSZ2_16 : bits == 21 ? CB_FRSZ2_21 : bits == 32 ? CB_FRSZ2_32
+         : (bits >= 3 && bits <= 32) ? CB_FRSZ2_BITS(bits) : -1;
 }
 
 int frsz2_compress(const double* x, int64_t n, int bits, uint32_t* exps, uint32_t* words,
                    int32_t* nonfinite_flag, void* stream) {
     const int f = format_of_bits(bits);
-    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (16, 21 or 32)", bits);
+    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (3 to 32)", bits);
     if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
     if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
     cb_basis V{f, (int32_t)n, 1, 0, words, exps};
@@ -129,7 +130,7 @@ int frsz2_compress(const double* x, int64_t n, int bits, uint32_t* exps, uint32_
 int frsz2_decompress(const uint32_t* exps, const uint32_t* words, int64_t n, int bits, double* x,
                      void* stream) {
     const int f = format_of_bits(bits);
-    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (16, 21 or 32)", bits);
+    if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (3 to 32)", bits);
     if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
     if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
     cb_basis V{f, (int32_t)n, 1, 0, const_cast<uint32_t*>(words), const_cast<uint32_t*>(exps)};

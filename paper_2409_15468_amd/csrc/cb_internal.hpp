@@ -44,10 +44,17 @@ __host__ __device__ inline int row_groups_dev(int np) { return (np + kRowsPerWG 
 constexpr int kProjectGroups = 1024;
 inline int project_groups(int64_t n) { int g = row_groups(n); return g < kProjectGroups ? g : kProjectGroups; }
 
-inline bool valid_format(int f) { return f >= CB_F64 && f <= CB_FRSZ2_32; }
+// Kernel template id of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l));
+// the bit count travels in BasisView::bits.
+constexpr int CB_FRSZ2_GEN = 6;
+inline bool generic_format(int f) { return f >= CB_FRSZ2_BITS(3) && f <= CB_FRSZ2_BITS(32); }
+inline bool valid_format(int f) { return (f >= CB_F64 && f <= CB_FRSZ2_32) || generic_format(f); }
 inline int frsz2_bits_of(int f) {
-    return f == CB_FRSZ2_16 ? 16 : f == CB_FRSZ2_21 ? 21 : f == CB_FRSZ2_32 ? 32 : 0;
+    return f == CB_FRSZ2_16 ? 16 : f == CB_FRSZ2_21 ? 21 : f == CB_FRSZ2_32 ? 32
+         : generic_format(f) ? f - CB_FRSZ2_GENERIC_BASE : 0;
 }
+// the template instance that runs format f
+inline int kernel_format(int f) { return generic_format(f) ? CB_FRSZ2_GEN : f; }
 int64_t column_bytes(int f, int64_t n);       // column stride (256-byte multiple)
 int64_t column_data_bytes(int f, int64_t n);  // bytes of one column's values
 int64_t exponent_words(int f, int64_t n);
@@ -60,6 +67,7 @@ struct BasisView {
     int64_t exp_stride;  // exponent words per column
     int32_t n;
     int32_t np;          // 32 * ceil(n/32)
+    int32_t bits;        // FRSZ2 l (0 for float formats)
 };
 inline BasisView view_of(const cb_basis& V) {
     BasisView b;
@@ -69,6 +77,7 @@ inline BasisView view_of(const cb_basis& V) {
     b.exp_stride = exponent_words(V.format, V.n);
     b.n = V.n;
     b.np = (int32_t)padded_rows(V.n);
+    b.bits = frsz2_bits_of(V.format);
     return b;
 }
 

@@ -1,5 +1,6 @@
-// Device-side storage codecs for basis columns: FRSZ2 (l = 16, 21, 32) and the
-// float64 / float32 / float16 baselines.
+// Device-side storage codecs for basis columns: FRSZ2 (specialised for l = 16,
+// 21, 32; any l in [3, 32] through the generic tile) and the float64 / float32
+// / float16 baselines.
 //
 // Access pattern.  A wavefront works on a tile of 512 consecutive rows of a
 // column; lane t owns 8 of them.  The lane-to-row map is chosen per format so
@@ -351,6 +352,79 @@ struct Tile<CB_FRSZ2_21> {
     }
 };
 
+// Any l in [3, 32] (the generic formats).  Lane t owns rows 8t .. 8t+7, i.e.
+// codes 8s .. 8s+7 (s = t % 4) of block t / 4, which start at bit 8 s l of the
+// block's l words: word 8 s l / 32, bit 8 s l % 32 of it.  The lane loads the
+// (at most 9) words that hold its 8 codes and walks them with a two-word
+// window that advances by one word whenever the bit position passes 32; the
+// window shifts use fixed register indices, so nothing spills.
+template <>
+struct Tile<CB_FRSZ2_GEN> {
+    uint32_t y[9];
+    uint32_t e;
+    uint32_t off;  // bit of the lane's first code in y[0]
+    int L;
+    template <int LM>
+    __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
+        L = V.bits;
+        const uint32_t* base = reinterpret_cast<const uint32_t*>(V.values + (int64_t)col * V.col_bytes);
+        const int r = tile0 + 8 * lane;
+        const bool live = (LM & kFull) || r < V.np;
+        const uint32_t start = 8u * (uint32_t)(lane & 3) * (uint32_t)L;
+        off = start & 31u;
+        // the codes end at bit start + 8 l - 1 <= 32 l - 1: inside the block
+        const int nw = (int)((off + 8u * (uint32_t)L + 31u) >> 5);
+        const uint32_t* p = base + (int64_t)(r >> 5) * L + (start >> 5);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) y[k] = (live && k < nw) ? ld4<(LM & kStream) != 0>(p + k) : 0u;
+        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
+    }
+    __device__ __forceinline__ void codes(uint32_t* c) const {
+        uint32_t w[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) w[k] = y[k];
+        const uint32_t mask = L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        uint32_t pos = off;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            c[q] = __builtin_amdgcn_alignbit(w[1], w[0], pos) & mask;
+            if (q < 7) {
+                pos += (uint32_t)L;
+                const bool adv = pos >= 32u;
+                // codes q+1 .. 7 need at most words 0 .. 7-q of the window
+#pragma unroll
+                for (int k = 0; k < 8 - q; ++k) w[k] = adv ? w[k + 1] : w[k];
+                pos = adv ? pos - 32u : pos;
+            }
+        }
+    }
+    __device__ __forceinline__ double m_of(uint32_t c) const {
+        return signed_mag(c & ((1u << (L - 1)) - 1u), c << (32 - L));
+    }
+    __device__ __forceinline__ double dot(const double* w) const {
+        uint32_t c[8];
+        codes(c);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum = fma(m_of(c[q]), w[q], sum);
+        return ldexp(sum, scale_exp(e, L));
+    }
+    __device__ __forceinline__ void axpy(double h, double* acc) const {
+        uint32_t c[8];
+        codes(c);
+        const double hs = ldexp(h, scale_exp(e, L));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = fma(hs, m_of(c[q]), acc[q]);
+    }
+    __device__ __forceinline__ void decode(double* out) const {
+        uint32_t c[8];
+        codes(c);
+        const int se = scale_exp(e, L);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) out[q] = ldexp(m_of(c[q]), se);
+    }
+};
+
 // Load U columns of a tile (load mode M).
 template <int FMT, int U, int LM>
 __device__ __forceinline__ void load_tiles(Tile<FMT>* t, const BasisView& V, const int* cols, int tile0,
@@ -373,6 +447,18 @@ __device__ __forceinline__ uint32_t frsz2_code(double v, uint32_t E) {
     const uint32_t drop = (uint32_t)(54 - L) + (Eeff - eeff);
     const uint32_t M = drop >= 53u ? 0u : (uint32_t)(sig >> drop);
     // step 4: the sign to the left of the significand
+    return ((hi >> 31) << (L - 1)) | M;
+}
+
+// The same code with l known only at run time (the generic formats).
+__device__ __forceinline__ uint32_t frsz2_code_rt(double v, uint32_t E, int L) {
+    const uint32_t hi = hi32(v), lo = lo32(v);
+    const uint32_t e = (hi >> 20) & 0x7FFu;
+    const uint32_t Eeff = E ? E : 1u;
+    const uint32_t eeff = e ? e : 1u;
+    const uint64_t sig = ((uint64_t)((hi & 0xFFFFFu) | (e ? 0x100000u : 0u)) << 32) | lo;
+    const uint32_t drop = (uint32_t)(54 - L) + (Eeff - eeff);
+    const uint32_t M = drop >= 53u ? 0u : (uint32_t)(sig >> drop);
     return ((hi >> 31) << (L - 1)) | M;
 }
 

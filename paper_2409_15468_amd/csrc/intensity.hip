@@ -62,12 +62,13 @@ int cb_intensity_run(const cb_basis* V, int32_t col, int32_t ops, double a, doub
     hipStream_t s = (hipStream_t)stream;
     const BasisView bv = view_of(*V);
     const int G = project_groups(V->n);
-    switch (V->format) {
+    switch (kernel_format(V->format)) {
     case CB_F64: k_intensity<CB_F64><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_F32: k_intensity<CB_F32><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_F16: k_intensity<CB_F16><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_16: k_intensity<CB_FRSZ2_16><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_21: k_intensity<CB_FRSZ2_21><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
+    case CB_FRSZ2_GEN: k_intensity<CB_FRSZ2_GEN><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     default: k_intensity<CB_FRSZ2_32><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     }
     CB_HIP(hipGetLastError());

@@ -74,12 +74,16 @@ constexpr int32_t kSmallN = 16384;
 constexpr int kMaxBatch = 512;
 constexpr int kBatchLanes = 2;
 
-static bool is_small(int32_t n, int32_t m) { return n <= kSmallN && m <= kBatchMaxRestart; }
+// The batched solver runs the fixed formats only; generic-l FRSZ2 requests go
+// to the solve lanes whatever their size.
+static bool is_small(int32_t n, int32_t m, int format) {
+    return n <= kSmallN && m <= kBatchMaxRestart && !generic_format(format);
+}
 
 static int64_t al256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 static int64_t request_bytes(int32_t n, int32_t nnz, int32_t m, int format) {
-    int64_t ws = is_small(n, m) ? batch_workspace_bytes(n, m, format) : cbgmres_workspace_bytes(n, m, format);
+    int64_t ws = is_small(n, m, format) ? batch_workspace_bytes(n, m, format) : cbgmres_workspace_bytes(n, m, format);
     if (ws < 0) return -1;
     // CSR + b + x on the device, plus the solver workspace
     return ws + al256((int64_t)(n + 1) * 4) + al256((int64_t)nnz * 4) + al256((int64_t)nnz * 8) +
@@ -194,7 +198,7 @@ static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_
     std::vector<std::shared_ptr<Request>> take;
     int64_t charged = S->charged;
     for (auto it = S->queue.begin(); it != S->queue.end();) {
-        const bool small = is_small((*it)->n, (*it)->m);
+        const bool small = is_small((*it)->n, (*it)->m, (*it)->format);
         if (small != batch_lane) {
             ++it;
             continue;
@@ -211,7 +215,7 @@ static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_
 
 static bool has_kind(const cb_server* S, bool batch_lane) {
     for (const auto& r : S->queue)
-        if (is_small(r->n, r->m) == batch_lane) return true;
+        if (is_small(r->n, r->m, r->format) == batch_lane) return true;
     return false;
 }
 

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
                                                     const double* __restrict__ divisor, double* __restrict__ y,
                                                     double* __restrict__ partials, unsigned char* __restrict__ values,
                                                     uint32_t* __restrict__ exps, int32_t* __restrict__ flag,
-                                                    const int* __restrict__ guard) {
+                                                    const int* __restrict__ guard, int bits) {
     if (guard && ld_ctl(guard) == 0) return;
     const double d = ld_ctl(divisor);
     const int lane = threadIdx.x & 63;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
         load_rows<FMT>(w, tile0, lane, n, v);
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;
-        bad |= encode_tile<FMT>(values, exps, np, tile0, lane, v);
+        bad |= encode_tile<FMT>(values, exps, np, tile0, lane, v, bits);
     }
     if (bad) atomicOr(flag, 1);
     double nrm;
@@ -255,14 +255,15 @@ void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, con
 #define CB_SS_CASE(F)                                                                                  \
     case F:                                                                                            \
         k_spmv_store<F><<<G, 256, 0, s>>>(A.n, b.np, A.row_ptr, A.col, A.val, lpr, w, divisor, y,      \
-                                          partials, vals, ex, flag, guard);                            \
+                                          partials, vals, ex, flag, guard, b.bits);                    \
         break;
-    switch (fmt) {
+    switch (kernel_format(fmt)) {
         CB_SS_CASE(CB_F64)
         CB_SS_CASE(CB_F32)
         CB_SS_CASE(CB_F16)
         CB_SS_CASE(CB_FRSZ2_16)
         CB_SS_CASE(CB_FRSZ2_21)
+        CB_SS_CASE(CB_FRSZ2_GEN)
         default:
         CB_SS_CASE(CB_FRSZ2_32)
     }

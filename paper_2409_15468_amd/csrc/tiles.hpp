@@ -18,9 +18,10 @@ namespace dev {
 // float16; float64 stored as is).  Groups of rows at or past np are not
 // written.  Returns true if a stored value is not finite (for frsz2: a block
 // whose exponent field is 2047).
+// bits: l of the generic FRSZ2 formats (ignored by the others).
 template <int FMT>
 __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, uint32_t* __restrict__ exps,
-                                            int np, int tile0, int lane, const double* v) {
+                                            int np, int tile0, int lane, const double* v, int bits = 0) {
     using M = Map<FMT>;
     bool bad = false;
     if constexpr (FMT == CB_F64 || FMT == CB_F32 || FMT == CB_F16) {
@@ -77,7 +78,43 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
         for (int q = 0; q < 8; ++q) E = max(E, exp_field(v[q]));
         E = group_max<2>(E);
         bad = E == 0x7FFu;
-        if constexpr (FMT == CB_FRSZ2_16) {
+        if constexpr (FMT == CB_FRSZ2_GEN) {
+            // The lane's 8 codes go to bits 8 s l .. 8 s l + 8 l - 1 of its
+            // block (s = lane % 4), streamed word by word through a 64-bit
+            // accumulator.  A word the lane shares with the previous lane of
+            // the block (its first, when it starts mid-word) is handed to that
+            // lane, which merges it into its own last word; the block's last
+            // lane always ends on a word boundary.
+            const int L = bits;
+            uint32_t c[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = frsz2_code_rt(v[q], E, L);
+            const uint32_t start = 8u * (uint32_t)(lane & 3) * (uint32_t)L;
+            const uint32_t off = start & 31u;
+            uint32_t* blk = reinterpret_cast<uint32_t*>(values) + (int64_t)(r >> 5) * L + (start >> 5);
+            const bool live = r < np;
+            uint64_t acc = 0;
+            uint32_t nb = off, head = 0;
+            int wi = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc |= (uint64_t)c[q] << nb;
+                nb += (uint32_t)L;
+                if (nb >= 32u) {
+                    const uint32_t wd = (uint32_t)acc;
+                    if (wi == 0 && off != 0u) head = wd;
+                    else if (live) blk[wi] = wd;
+                    ++wi;
+                    acc >>= 32;
+                    nb -= 32u;
+                }
+            }
+            const uint32_t next_head = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)head, 0xF9, 0xF, 0xF, false);
+            if (live) {
+                if (nb > 0u) blk[wi] = (uint32_t)acc | next_head;
+                if ((lane & 3) == 0) exps[r >> 5] = E;
+            }
+        } else if constexpr (FMT == CB_FRSZ2_16) {
             uint32_t c[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) c[q] = frsz2_code<16>(v[q], E);

@@ -53,18 +53,30 @@ def test_size_queries_match_storage_definitions():
             assert V.column_data_bytes() == data
             ew = cb.cb_basis_exponent_words(fmt, n)
             assert ew == ((n + 31) // 32 if fmt.startswith("frsz2") else 0)
-    assert cb.frsz2_value_words(10, 17) == -1
+    for l in range(3, 33):
+        assert cb.frsz2_value_words(1000, l) == l * 32
+        f = cb.frsz2_bits_format(l)
+        assert cb.cb_basis_column_bytes(f, 1000) == (l * 32 * 4 + 255) // 256 * 256
+        assert cb.cb_basis_exponent_words(f, 1000) == 32
+        assert oracle.col_bytes(f, 1000) == l * 32 * 4
+    assert cb.frsz2_value_words(10, 2) == -1 and cb.frsz2_value_words(10, 33) == -1
     assert cb.cb_basis_column_bytes(9, 10) == -1
+    assert cb.cb_basis_column_bytes(cb.CB_FRSZ2_GENERIC_BASE + 2, 10) == -1
+    assert cb.cb_basis_column_bytes(cb.CB_FRSZ2_GENERIC_BASE + 33, 10) == -1
+    assert cb.cbgmres_batch_workspace_bytes(1000, 30, cb.frsz2_bits_format(12)) == -1
     assert cb.cbgmres_workspace_bytes(1000, 10, "frsz2_32") > 11 * cb.cb_basis_column_bytes("frsz2_32", 1000)
     assert cb.Server.request_bytes(1000, 5000, 10, "float32") > cb.cbgmres_workspace_bytes(1000, 10, "float32")
 
 
 def test_argument_errors_without_device_work():
     L = cb.lib()
-    assert L.frsz2_compress(None, 10, 17, None, None, None, None) == cb.CB_ERR_UNSUPPORTED_BITS
+    for bad_bits in (2, 33, 0, -1):
+        assert L.frsz2_compress(None, 10, bad_bits, None, None, None, None) == cb.CB_ERR_UNSUPPORTED_BITS
+        assert L.frsz2_decompress(None, None, 10, bad_bits, None, None) == cb.CB_ERR_UNSUPPORTED_BITS
+    assert b"3 to 32" in L.cb_last_error()
     assert L.frsz2_compress(None, 10, 32, None, None, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_compress(None, 10, 17, None, None, None, None) == cb.CB_ERR_INVALID_ARG
     assert L.frsz2_decompress(None, None, 0, 16, None, None) == cb.CB_ERR_INVALID_ARG
-    assert b"16, 21 or 32" in L.cb_last_error() or L.cb_last_error()
     A = cb.cb_csr(10, 0, None, None, None)
     res = cb.cb_result()
     st = L.cbgmres_solve(C.byref(A), None, None, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res), None)

@@ -2,7 +2,8 @@
 inputs (lockstep at the kernel level):
 
 * cb_basis_store: v = w / d by IEEE division and the stored column are
-  bit-exact against numpy division and the oracle's encoder, all six formats;
+  bit-exact against numpy division and the oracle's encoder, all six formats
+  and generic-codec FRSZ2 widths;
 * cb_cgs_project: h = D(V)^T w within 1e-12 of the oracle, relative to
   sum_k |v_ik w_k| (the Hessenberg tolerance);
 * cb_cgs_subtract / cb_basis_combine: w -/+= D(V) h within 1e-14 relative to
@@ -23,6 +24,8 @@ def u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 FORMATS = list(oracle.FORMATS)
+# generic-codec widths (frsz2g_32: the generic codec at l = 32)
+GENERIC = ["frsz2_3", "frsz2_7", "frsz2_12", "frsz2_27", "frsz2g_32"]
 
 
 def build_basis(fmt, n, j, seed):
@@ -41,7 +44,7 @@ def build_basis(fmt, n, j, seed):
     return V, enc, dec
 
 
-@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("fmt", FORMATS + GENERIC)
 @pytest.mark.parametrize("n", [777, 4101, 2048 * 5 + 13])
 def test_store_bit_exact_with_division(fmt, n):
     w = mixed_vector(n, seed=n, spread=4)
@@ -74,7 +77,7 @@ def test_store_float16_overflow_flag():
     assert int(flag.item()) == 1
 
 
-@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("fmt", FORMATS + GENERIC)
 @pytest.mark.parametrize("n,j", [(777, 1), (4101, 5), (2048 * 5 + 13, 17), (3000, 70)])
 def test_project_subtract_combine(fmt, n, j):
     V, enc, dec = build_basis(fmt, n, j, seed=n + j)

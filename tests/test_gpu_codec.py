@@ -1,7 +1,9 @@
 """GPU parity of the FRSZ2 codec (frsz2_compress / frsz2_decompress through
 the C ABI) against the CPU oracle: compressed words and exponents bit-exact,
-decompressed values bit-exact, for l = 16, 21, 32, ragged sizes, adversarial
-blocks, non-finite input, and sampled blocks of a full 2^24-value column."""
+decompressed values bit-exact, for every l in [3, 32] (16, 21 and 32 on their
+specialised kernels, the rest on the generic codec), ragged sizes, adversarial
+blocks, non-finite input, and sampled blocks of a full 2^24-value column; the
+generic codec at l = 16, 21, 32 stores the specialised kernels' bits."""
 import numpy as np
 import pytest
 
@@ -17,6 +19,7 @@ def u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 BITS = [16, 21, 32]
+ALL_BITS = list(range(3, 33))  # 16, 21, 32 on their own kernels, the rest on the generic codec
 SIZES = [1, 31, 32, 33, 1000, 2048 * 3 + 17, 100003]
 
 
@@ -28,7 +31,7 @@ def gpu_roundtrip(x, bits):
     return u32(exps), u32(words), dec.cpu().numpy()
 
 
-@pytest.mark.parametrize("bits", BITS)
+@pytest.mark.parametrize("bits", ALL_BITS)
 @pytest.mark.parametrize("n", SIZES)
 def test_compress_bit_exact_random(bits, n):
     x = mixed_vector(n, seed=n + bits)
@@ -41,7 +44,7 @@ def test_compress_bit_exact_random(bits, n):
     assert np.array_equal(d.view(np.uint64), od.view(np.uint64))
 
 
-@pytest.mark.parametrize("bits", BITS)
+@pytest.mark.parametrize("bits", ALL_BITS)
 def test_compress_bit_exact_adversarial(bits):
     x = adversarial_blocks()
     e, w, d = gpu_roundtrip(x, bits)
@@ -51,7 +54,7 @@ def test_compress_bit_exact_adversarial(bits):
     assert np.array_equal(d.view(np.uint64), oracle.frsz2_decode(oe, ow, x.size, bits).view(np.uint64))
 
 
-@pytest.mark.parametrize("bits", BITS)
+@pytest.mark.parametrize("bits", BITS + [3, 9, 27])
 def test_nonfinite_flag(bits):
     x = mixed_vector(200, seed=3)
     x[70] = np.inf
@@ -74,7 +77,7 @@ def test_nonfinite_flag(bits):
     assert int(flag.item()) == 0
 
 
-@pytest.mark.parametrize("bits", BITS)
+@pytest.mark.parametrize("bits", BITS + [5, 12, 27])
 def test_full_size_column_sampled(bits):
     """A 2^24-value column of the tall-skinny benchmark basis (block scales
     10^u, u ~ U(-8,0)): sampled blocks bit-exact against the oracle, and the
@@ -99,3 +102,22 @@ def test_full_size_column_sampled(bits):
         oe, ow, _ = oracle.frsz2_encode(col[32 * b:32 * b + 32], bits)
         assert e[b] == oe[0]
         np.testing.assert_array_equal(w[b], ow)
+
+
+@pytest.mark.parametrize("l", BITS)
+def test_generic_codec_stores_the_specialised_bits(l):
+    """The generic-l formats at l = 16, 21, 32 store exactly the words and
+    exponents of the specialised formats, and decode to the same values."""
+    n = 2048 * 2 + 45
+    x = mixed_vector(n, seed=40 + l)
+    spec = cb.Basis.empty(f"frsz2_{l}", n, 1)
+    gen = cb.Basis.empty(cb.frsz2_bits_format(l), n, 1)
+    xd = torch.from_numpy(x).cuda()
+    cb.cb_basis_store(spec, 0, xd)
+    cb.cb_basis_store(gen, 0, xd)
+    torch.cuda.synchronize()
+    assert np.array_equal(spec.column(0).cpu().numpy(), gen.column(0).cpu().numpy())
+    assert np.array_equal(u32(spec.column_exps(0)), u32(gen.column_exps(0)))
+    a = cb.cb_basis_load(spec, 0).cpu().numpy()
+    b = cb.cb_basis_load(gen, 0).cpu().numpy()
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))

@@ -10,7 +10,7 @@ import paper_2409_15468_amd as cb
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-FORMATS = list(oracle.FORMATS)
+FORMATS = list(oracle.FORMATS) + ["frsz2_9", "frsz2_27"]  # the last two on the generic codec
 
 
 @pytest.mark.parametrize("fmt", FORMATS)

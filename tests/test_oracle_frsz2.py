@@ -16,6 +16,9 @@ import pytest
 import oracle
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "frsz2_worked.txt")
+# l is a free parameter of the format (Section IV-A): the fixed widths and a
+# spread of others, odd and even, below and above 16
+ALL_L = [3, 4, 7, 8, 12, 13, 16, 17, 21, 24, 27, 31, 32]
 BLOCK_A = [1.0, -0.75, 0.1, 0.0, -0.0, 3e-300, 2.0 ** -30, -(1 - 2.0 ** -53)] + [0.0] * 24
 BLOCK_B = [0.5, 1e-5, -0.3]
 
@@ -119,7 +122,7 @@ def test_worked_vector_words_and_decode():
 
 
 # ---------------------------------------------------------------- value definition and packing
-@pytest.mark.parametrize("l", [16, 21, 32])
+@pytest.mark.parametrize("l", ALL_L)
 @pytest.mark.parametrize("spread", [0, 3, 12, 40])
 def test_encode_matches_grid_definition_and_packer(l, spread):
     rng = np.random.default_rng(100 + l + spread)
@@ -135,7 +138,7 @@ def test_encode_matches_grid_definition_and_packer(l, spread):
         assert [_bits(v) for v in dec] == [_bits(v) for v in ref]
 
 
-@pytest.mark.parametrize("l", [16, 21, 32])
+@pytest.mark.parametrize("l", ALL_L)
 def test_error_bound_sign_and_monotone(l):
     rng = np.random.default_rng(7 + l)
     x = _random_blocks(rng, 200, 6)
@@ -159,7 +162,7 @@ def test_error_bound_sign_and_monotone(l):
         assert np.all(np.diff(d[32 * b:32 * b + 32][o]) >= 0)
 
 
-@pytest.mark.parametrize("l", [16, 21, 32])
+@pytest.mark.parametrize("l", ALL_L)
 def test_idempotence_and_exact_roundtrip(l):
     rng = np.random.default_rng(11 * l)
     x = _random_blocks(rng, 100, 5)
@@ -183,7 +186,7 @@ def test_idempotence_and_exact_roundtrip(l):
         assert unpack_codes(w3[b * l:(b + 1) * l], l) == [int(c) for c in codes[b]]
 
 
-@pytest.mark.parametrize("l", [16, 21, 32])
+@pytest.mark.parametrize("l", ALL_L)
 def test_power_of_two_scaling_changes_only_exponent(l):
     rng = np.random.default_rng(5)
     x = rng.standard_normal(32 * 20) * 10.0 ** rng.uniform(-5, 0, 32 * 20)
@@ -194,7 +197,7 @@ def test_power_of_two_scaling_changes_only_exponent(l):
         np.testing.assert_array_equal(e1.astype(np.int64), e0.astype(np.int64) + t)
 
 
-@pytest.mark.parametrize("l", [16, 21, 32])
+@pytest.mark.parametrize("l", ALL_L)
 def test_random_access_route_equals_closed_form(l):
     rng = np.random.default_rng(3 * l)
     x = _random_blocks(rng, 30, 20)
@@ -226,6 +229,32 @@ def test_bruteforce_all_16bit_codes(E):
     assert not bad
     np.testing.assert_array_equal(e2, exps)
     np.testing.assert_array_equal(w2, words.ravel())
+
+
+@pytest.mark.parametrize("l", [3, 5, 8, 11])
+def test_bruteforce_every_code_of_small_widths(l):
+    """Every l-bit code in every slot of a block, at a small, a middle and the
+    top exponent: decoding then encoding gives the codes and exponent back."""
+    for E in (1, 1023, 2046):
+        codes = np.arange(1 << l, dtype=np.int64)
+        anchor = 1 << (l - 2)
+        per = 31
+        nblk = (codes.size + per - 1) // per
+        for shift in range(32):  # every code in every slot
+            blocks = np.zeros((nblk, 32), np.int64)
+            flat = np.zeros(nblk * per, np.int64)
+            flat[:codes.size] = np.roll(codes, shift)
+            slots = [q for q in range(32) if q != shift % 32]
+            blocks[:, slots] = flat.reshape(nblk, per)
+            blocks[:, shift % 32] = anchor
+            vals = np.array([[grid_decode(E, int(c), l) for c in blocks[b]] for b in range(nblk)]).ravel()
+            e2, w2, bad = oracle.frsz2_encode(vals, l)
+            assert not bad
+            np.testing.assert_array_equal(e2, np.full(nblk, E, np.uint32))
+            for b in range(nblk):
+                assert unpack_codes(w2[b * l:(b + 1) * l], l) == [int(c) for c in blocks[b]]
+            if l > 5:
+                break  # one arrangement suffices for the wider codes
 
 
 def test_zero_and_subnormal_blocks():
