@@ -446,6 +446,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--all-formats", action="store_true",
                     help="also time the sweep solve with the float32, float16, frsz2_16 and frsz2_21 bases")
+    ap.add_argument("--extra-formats", default="",
+                    help="further basis formats to time in the sweep solve, e.g. frsz2b64_32,frsz2_24")
     ap.add_argument("--no-micro", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="microbench only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -584,8 +586,10 @@ def main():
                         "reorths": r_d["reorths"], "rel_residual": r_d["rel_residual"]},
             "speedup_frsz2_32_vs_float64": t_d / t_z,
         }
-        if args.all_formats:
-            for fmt in ("float32", "float16", "frsz2_16", "frsz2_21"):
+        extra = (["float32", "float16", "frsz2_16", "frsz2_21"] if args.all_formats else []) + \
+            [f for f in args.extra_formats.split(",") if f]
+        if extra:
+            for fmt in extra:
                 log(f"bench: {fmt} solves")
                 t_f, r_f = timed_solves(cb, torch, A, b, x, fmt, m, tol, args.steps, args.warmup, ws)
                 xf = x.cpu().numpy()

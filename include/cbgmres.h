@@ -56,7 +56,9 @@ typedef enum cb_basis_format {
     CB_F16 = 2,
     CB_FRSZ2_16 = 3,
     CB_FRSZ2_21 = 4,
-    CB_FRSZ2_32 = 5
+    CB_FRSZ2_32 = 5,
+    CB_FRSZ2_16_B64 = 6,  /* frsz2_16 and frsz2_32 with blocks of 64 values */
+    CB_FRSZ2_32_B64 = 7
 } cb_basis_format;
 
 /* FRSZ2 with any l in [3, 32] (l is a free parameter of the format, Section
@@ -64,10 +66,21 @@ typedef enum cb_basis_format {
  * walk their codes with a runtime bit offset.  The storage layout and the
  * codes are those of the fixed formats: CB_FRSZ2_BITS(16), (21) and (32)
  * store the same bits as CB_FRSZ2_16, _21 and _32, which have specialised
- * (faster) kernels.  Every entry point that takes a format accepts these,
- * except the batched small-system solver. */
+ * (faster) kernels.  Every entry point that takes a format accepts these and
+ * the block-64 formats below, except the batched small-system solver. */
 #define CB_FRSZ2_GENERIC_BASE 64
 #define CB_FRSZ2_BITS(l) (CB_FRSZ2_GENERIC_BASE + (l))
+
+/* Blocks of 64 values (one wavefront's 64 lanes x 8 values cover 8 blocks):
+ * 64 consecutive values share one exponent word and their codes form one
+ * 64 l-bit stream of 2 l words; a column has ceil(n/64) exponent words and
+ * rows n .. 64*ceil(n/64)-1 stored as +0.0.  The paper fixes 32 (Section
+ * IV-C, item 2; other sizes ran slower end to end on its GPU); these formats
+ * let the trade-off be measured on a 64-wide machine.  CB_FRSZ2_16_B64 and
+ * CB_FRSZ2_32_B64 have specialised kernels; CB_FRSZ2_B64_BITS(l), any l in
+ * [3, 32], runs the generic codec. */
+#define CB_FRSZ2_B64_GENERIC_BASE 128
+#define CB_FRSZ2_B64_BITS(l) (CB_FRSZ2_B64_GENERIC_BASE + (l))
 
 const char* cb_status_string(int status);
 const char* cb_last_error(void);

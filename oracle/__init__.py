@@ -21,7 +21,15 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FORMATS = {"float64": 0, "float32": 1, "float16": 2, "frsz2_16": 3, "frsz2_21": 4, "frsz2_32": 5}
-FRSZ2_BITS = {3: 16, 4: 21, 5: 32, **{64 + l: l for l in range(3, 33)}}
+# FRSZ2 with blocks of 64 values (6, 7), and any l with blocks of 32 (64 + l) or 64 (128 + l)
+FORMATS_B64 = {"frsz2b64_16": 6, "frsz2b64_32": 7}
+FRSZ2_BITS = {3: 16, 4: 21, 5: 32, 6: 16, 7: 32, **{64 + l: l for l in range(3, 33)},
+              **{128 + l: l for l in range(3, 33)}}
+
+
+def block_size(fmt) -> int:
+    f = _fmt(fmt)
+    return 64 if f in (6, 7) or 128 + 3 <= f <= 128 + 32 else 32
 
 
 def build() -> str:
@@ -48,6 +56,10 @@ def lib():
             "or_frsz2_encode": (i32, [P, i64, i32, P, P]),
             "or_frsz2_decode": (None, [P, P, i64, i32, P]),
             "or_frsz2_decode_value": (d, [P, P, i64, i32]),
+            "or_frsz2_encode_bs": (i32, [P, i64, i32, i32, P, P]),
+            "or_frsz2_decode_bs": (None, [P, P, i64, i32, i32, P]),
+            "or_frsz2_decode_value_bs": (d, [P, P, i64, i32, i32]),
+            "or_basis_exp_words": (i64, [i32, i64]),
             "or_f16_from_f64": (C.c_uint16, [d]),
             "or_f64_from_f16": (d, [C.c_uint16]),
             "or_basis_col_bytes": (i64, [i32, i64]),
@@ -87,12 +99,17 @@ def frsz2_any(l: int) -> int:
 
 
 def _fmt(fmt) -> int:
-    """A format name or number: the six names above, "frsz2_<l>" for any other
-    l in [3, 32], "frsz2g_<l>" for the number 64 + l of any l."""
+    """A format name or number: the names above, "frsz2_<l>" for any other l
+    in [3, 32], "frsz2g_<l>" for the number 64 + l of any l; with blocks of 64,
+    "frsz2b64_<l>" (128 + l unless l is 16 or 32) and "frsz2b64g_<l>" (128 + l)."""
     if not isinstance(fmt, str):
         return int(fmt)
     if fmt in FORMATS:
         return FORMATS[fmt]
+    if fmt in FORMATS_B64:
+        return FORMATS_B64[fmt]
+    if fmt.startswith("frsz2b64_") or fmt.startswith("frsz2b64g_"):
+        return 64 + frsz2_any(int(fmt.split("_")[1]))
     if fmt.startswith("frsz2_") or fmt.startswith("frsz2g_"):
         return frsz2_any(int(fmt.split("_")[1]))
     raise KeyError(fmt)
@@ -103,28 +120,37 @@ def nblocks(n: int) -> int:
 
 
 # ---------------------------------------------------------------- FRSZ2 codec
-def frsz2_encode(x: np.ndarray, bits: int):
-    """Returns (exps uint32[ceil(n/32)], words uint32[bits*ceil(n/32)], nonfinite)."""
+def frsz2_encode(x: np.ndarray, bits: int, bs: int = 32):
+    """Blocks of bs (32 or 64) values.  Returns (exps uint32[ceil(n/bs)],
+    words uint32[(bs/32)*bits*ceil(n/bs)], nonfinite)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
-    nb = nblocks(x.size)
+    nb = (x.size + bs - 1) // bs
     exps = np.zeros(nb, np.uint32)
-    words = np.zeros(nb * bits, np.uint32)
-    bad = lib().or_frsz2_encode(_p(x), x.size, bits, _p(exps), _p(words))
+    words = np.zeros(nb * bits * (bs // 32), np.uint32)
+    if bs == 32:
+        bad = lib().or_frsz2_encode(_p(x), x.size, bits, _p(exps), _p(words))
+    else:
+        bad = lib().or_frsz2_encode_bs(_p(x), x.size, bits, bs, _p(exps), _p(words))
     return exps, words, bool(bad)
 
 
-def frsz2_decode(exps: np.ndarray, words: np.ndarray, n: int, bits: int) -> np.ndarray:
+def frsz2_decode(exps: np.ndarray, words: np.ndarray, n: int, bits: int, bs: int = 32) -> np.ndarray:
     exps = np.ascontiguousarray(exps, dtype=np.uint32)
     words = np.ascontiguousarray(words, dtype=np.uint32)
     out = np.empty(n, np.float64)
-    lib().or_frsz2_decode(_p(exps), _p(words), n, bits, _p(out))
+    if bs == 32:
+        lib().or_frsz2_decode(_p(exps), _p(words), n, bits, _p(out))
+    else:
+        lib().or_frsz2_decode_bs(_p(exps), _p(words), n, bits, bs, _p(out))
     return out
 
 
-def frsz2_decode_value(exps: np.ndarray, words: np.ndarray, i: int, bits: int) -> float:
+def frsz2_decode_value(exps: np.ndarray, words: np.ndarray, i: int, bits: int, bs: int = 32) -> float:
     exps = np.ascontiguousarray(exps, dtype=np.uint32)
     words = np.ascontiguousarray(words, dtype=np.uint32)
-    return lib().or_frsz2_decode_value(_p(exps), _p(words), i, bits)
+    if bs == 32:
+        return lib().or_frsz2_decode_value(_p(exps), _p(words), i, bits)
+    return lib().or_frsz2_decode_value_bs(_p(exps), _p(words), i, bits, bs)
 
 
 # ---------------------------------------------------------------- casts
@@ -141,14 +167,18 @@ def col_bytes(fmt, n: int) -> int:
     return int(lib().or_basis_col_bytes(_fmt(fmt), n))
 
 
+def exp_words(fmt, n: int) -> int:
+    return int(lib().or_basis_exp_words(_fmt(fmt), n))
+
+
 def basis_encode(fmt, x: np.ndarray):
     """Q(x) for one column.  Returns (values as uint8 bytes, exps uint32, nonfinite)."""
     f = _fmt(fmt)
     x = np.ascontiguousarray(x, dtype=np.float64)
     vals = np.zeros(col_bytes(f, x.size), np.uint8)
-    exps = np.zeros(max(1, nblocks(x.size)), np.uint32)
+    exps = np.zeros(max(1, exp_words(f, x.size)), np.uint32)
     bad = lib().or_basis_encode(f, _p(x), x.size, _p(vals), _p(exps))
-    return vals, exps, bool(bad)
+    return vals, exps[:exp_words(f, x.size)] if exp_words(f, x.size) else exps, bool(bad)
 
 
 def basis_decode(fmt, vals: np.ndarray, exps: np.ndarray, n: int) -> np.ndarray:

@@ -25,11 +25,14 @@
 
 /* Basis storage formats (the "basis knob").  The numbering is part of the
  * storage contract that the tests rely on. */
-enum { OR_F64 = 0, OR_F32 = 1, OR_F16 = 2, OR_FRSZ2_16 = 3, OR_FRSZ2_21 = 4, OR_FRSZ2_32 = 5 };
+enum { OR_F64 = 0, OR_F32 = 1, OR_F16 = 2, OR_FRSZ2_16 = 3, OR_FRSZ2_21 = 4, OR_FRSZ2_32 = 5,
+       OR_FRSZ2_16_B64 = 6, OR_FRSZ2_32_B64 = 7 };
 
-#define OR_BS 32 /* FRSZ2 block size, fixed (Section IV-C, item 2) */
+#define OR_BS 32     /* FRSZ2 block size of the paper's runs (Section IV-C, item 2) */
+#define OR_BS_MAX 64 /* the other block size offered: 64 values per exponent */
 
 static int64_t nblocks_of(int64_t n) { return (n + OR_BS - 1) / OR_BS; }
+static int64_t nblocks_bs(int64_t n, int bs) { return (n + bs - 1) / bs; }
 
 /* ------------------------------------------------------------------------ */
 /* FRSZ2 compression: the six steps of Section IV-A, Eq. (1)-(2).           */
@@ -45,17 +48,17 @@ static void ieee_split(double x, unsigned* s, unsigned* e, uint64_t* f) {
     *f = b & ((UINT64_C(1) << 52) - 1);
 }
 
-/* Encode one block of 32 values (missing tail values already replaced by
- * +0.0).  Writes the block's l words (the bit stream of the 32 codes, code q
- * at bits [q*l, (q+1)*l), LSB first, little-endian 32-bit words) and returns
- * the stored exponent word.  *nonfinite is set when the block holds Inf/NaN
- * (its words are then meaningless). */
-static uint32_t frsz2_encode_block(const double* x, int l, uint32_t* words, int* nonfinite) {
-    unsigned s[OR_BS], e[OR_BS];
-    uint64_t f[OR_BS];
+/* Encode one block of bs values, bs = 32 or 64 (missing tail values already
+ * replaced by +0.0).  Writes the block's bs*l/32 words (the bit stream of the
+ * codes, code q at bits [q*l, (q+1)*l), LSB first, little-endian 32-bit
+ * words) and returns the stored exponent word.  *nonfinite is set when the
+ * block holds Inf/NaN (its words are then meaningless). */
+static uint32_t frsz2_encode_block(const double* x, int l, int bs, uint32_t* words, int* nonfinite) {
+    unsigned s[OR_BS_MAX], e[OR_BS_MAX];
+    uint64_t f[OR_BS_MAX];
     unsigned emax = 0;
     /* Step 1: extract every exponent and find the block maximum. */
-    for (int q = 0; q < OR_BS; ++q) {
+    for (int q = 0; q < bs; ++q) {
         ieee_split(x[q], &s[q], &e[q], &f[q]);
         if (e[q] > emax) emax = e[q];
     }
@@ -63,8 +66,8 @@ static uint32_t frsz2_encode_block(const double* x, int l, uint32_t* words, int*
     /* A block of zeros and subnormals normalises against exponent field 1,
      * the exponent at which subnormals live. */
     unsigned emax_eff = emax ? emax : 1;
-    memset(words, 0, (size_t)l * 4);
-    for (int q = 0; q < OR_BS; ++q) {
+    memset(words, 0, (size_t)l * 4 * (bs / 32));
+    for (int q = 0; q < bs; ++q) {
         /* Step 2: significand with the usually implicit leading 1 made
          * explicit (subnormals have a leading 0 and live at exponent 1). */
         unsigned e_eff = e[q] ? e[q] : 1;
@@ -88,19 +91,25 @@ static uint32_t frsz2_encode_block(const double* x, int l, uint32_t* words, int*
     return emax;
 }
 
-/* Compress n values.  exps has ceil(n/32) entries, words l*ceil(n/32).
- * Returns 1 if any block held a non-finite value, else 0. */
-int or_frsz2_encode(const double* x, int64_t n, int l, uint32_t* exps, uint32_t* words) {
+/* Compress n values in blocks of bs (32 or 64).  exps has ceil(n/bs)
+ * entries, words (bs/32)*l*ceil(n/bs).  Returns 1 if any block held a
+ * non-finite value, else 0. */
+int or_frsz2_encode_bs(const double* x, int64_t n, int l, int bs, uint32_t* exps, uint32_t* words) {
     int nonfinite = 0;
-    double blk[OR_BS];
-    for (int64_t b = 0; b < nblocks_of(n); ++b) {
-        for (int q = 0; q < OR_BS; ++q) {
-            int64_t i = b * OR_BS + q;
+    double blk[OR_BS_MAX];
+    const int64_t bw = (int64_t)l * (bs / 32); /* words per block */
+    for (int64_t b = 0; b < nblocks_bs(n, bs); ++b) {
+        for (int q = 0; q < bs; ++q) {
+            int64_t i = b * bs + q;
             blk[q] = i < n ? x[i] : 0.0; /* pad the tail with +0.0 */
         }
-        exps[b] = frsz2_encode_block(blk, l, words + b * l, &nonfinite);
+        exps[b] = frsz2_encode_block(blk, l, bs, words + b * bw, &nonfinite);
     }
     return nonfinite;
+}
+
+int or_frsz2_encode(const double* x, int64_t n, int l, uint32_t* exps, uint32_t* words) {
+    return or_frsz2_encode_bs(x, n, l, OR_BS, exps, words);
 }
 
 /* Read code q of a block's bit stream. */
@@ -117,11 +126,12 @@ static uint64_t frsz2_code(const uint32_t* blockwords, int l, int q) {
  * stored exponent E is (-1)^sign * M * 2^(E_eff - 1023 - (l-2)), M the l-1
  * magnitude bits (integer bit plus l-2 fraction bits).  Every such value is
  * a multiple of 2^-1074 below 2^1024, hence exactly representable. */
-void or_frsz2_decode(const uint32_t* exps, const uint32_t* words, int64_t n, int l, double* x) {
+void or_frsz2_decode_bs(const uint32_t* exps, const uint32_t* words, int64_t n, int l, int bs, double* x) {
+    const int64_t bw = (int64_t)l * (bs / 32);
     for (int64_t i = 0; i < n; ++i) {
-        int64_t b = i / OR_BS;
-        int q = (int)(i % OR_BS);
-        uint64_t c = frsz2_code(words + b * l, l, q);
+        int64_t b = i / bs;
+        int q = (int)(i % bs);
+        uint64_t c = frsz2_code(words + b * bw, l, q);
         uint64_t M = c & ((UINT64_C(1) << (l - 1)) - 1);
         int neg = (int)((c >> (l - 1)) & 1u);
         int E = (int)exps[b];
@@ -131,18 +141,22 @@ void or_frsz2_decode(const uint32_t* exps, const uint32_t* words, int64_t n, int
     }
 }
 
+void or_frsz2_decode(const uint32_t* exps, const uint32_t* words, int64_t n, int l, double* x) {
+    or_frsz2_decode_bs(exps, words, n, l, OR_BS, x);
+}
+
 /* Random-access decompression of value i by the four steps of Section IV-B:
  * read the block exponent and the code; split off the sign and count the
  * leading zeros k of the significand; drop them and the explicit 1, giving
  * the exponent e = E - k; merge sign, exponent and significand into IEEE bits.
  * An independent route to the same value as the closed form above. */
-double or_frsz2_decode_value(const uint32_t* exps, const uint32_t* words, int64_t i, int l) {
-    int64_t b = i / OR_BS;
-    int q = (int)(i % OR_BS);
+double or_frsz2_decode_value_bs(const uint32_t* exps, const uint32_t* words, int64_t i, int l, int bs) {
+    int64_t b = i / bs;
+    int q = (int)(i % bs);
     /* Step 1 */
     unsigned E = exps[b];
     unsigned Eeff = E ? E : 1;
-    uint64_t c = frsz2_code(words + b * l, l, q);
+    uint64_t c = frsz2_code(words + b * (int64_t)l * (bs / 32), l, q);
     /* Step 2 */
     uint64_t sign = (c >> (l - 1)) & 1u;
     uint64_t M = c & ((UINT64_C(1) << (l - 1)) - 1);
@@ -166,6 +180,10 @@ double or_frsz2_decode_value(const uint32_t* exps, const uint32_t* words, int64_
     double v;
     memcpy(&v, &bits, 8);
     return v;
+}
+
+double or_frsz2_decode_value(const uint32_t* exps, const uint32_t* words, int64_t i, int l) {
+    return or_frsz2_decode_value_bs(exps, words, i, l, OR_BS);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -212,18 +230,27 @@ double or_f64_from_f16(uint16_t h) {
 
 /* ------------------------------------------------------------------------ */
 /* Basis column storage.  Column c of an ncols-wide basis over n rows uses    */
-/* col_bytes = nb*32*{8,4,2} for float64/32/16 and nb*l*4 for frsz2_l (nb =   */
-/* ceil(n/32)); frsz2 columns also own nb exponent words.  Rows n..32*nb-1    */
-/* hold +0.0.                                                                */
+/* col_bytes = nb*32*{8,4,2} for float64/32/16 (nb = ceil(n/32)) and          */
+/* nbs*(bs/32)*l*4 for frsz2_l with blocks of bs values (nbs = ceil(n/bs));   */
+/* frsz2 columns also own nbs exponent words.  Rows past n hold +0.0.         */
 /* ------------------------------------------------------------------------ */
 
-/* FRSZ2 with any l in [3, 32]: format number 64 + l (l is a free parameter of
- * the format, Section IV-A; 16, 21 and 32 also have the numbers above). */
+/* FRSZ2 with any l in [3, 32]: format number 64 + l with blocks of 32 values,
+ * 128 + l with blocks of 64 (l is a free parameter of the format, Section
+ * IV-A; the fixed widths also have the numbers above). */
 #define OR_FRSZ2_ANY(l) (64 + (l))
+#define OR_FRSZ2_B64_ANY(l) (128 + (l))
 
 static int frsz2_bits(int fmt) {
     if (fmt >= OR_FRSZ2_ANY(3) && fmt <= OR_FRSZ2_ANY(32)) return fmt - 64;
-    return fmt == OR_FRSZ2_16 ? 16 : fmt == OR_FRSZ2_21 ? 21 : fmt == OR_FRSZ2_32 ? 32 : 0;
+    if (fmt >= OR_FRSZ2_B64_ANY(3) && fmt <= OR_FRSZ2_B64_ANY(32)) return fmt - 128;
+    return fmt == OR_FRSZ2_16 || fmt == OR_FRSZ2_16_B64 ? 16 : fmt == OR_FRSZ2_21 ? 21
+         : fmt == OR_FRSZ2_32 || fmt == OR_FRSZ2_32_B64 ? 32 : 0;
+}
+
+static int frsz2_bs(int fmt) {
+    return fmt == OR_FRSZ2_16_B64 || fmt == OR_FRSZ2_32_B64 ||
+           (fmt >= OR_FRSZ2_B64_ANY(3) && fmt <= OR_FRSZ2_B64_ANY(32)) ? 64 : 32;
 }
 
 int64_t or_basis_col_bytes(int fmt, int64_t n) {
@@ -232,8 +259,13 @@ int64_t or_basis_col_bytes(int fmt, int64_t n) {
     case OR_F64: return nb * 32 * 8;
     case OR_F32: return nb * 32 * 4;
     case OR_F16: return nb * 32 * 2;
-    default: return nb * frsz2_bits(fmt) * 4;
+    default: return nblocks_bs(n, frsz2_bs(fmt)) * (frsz2_bs(fmt) / 32) * frsz2_bits(fmt) * 4;
     }
+}
+
+/* exponent words of one column: ceil(n / bs) for frsz2, 0 for float formats */
+int64_t or_basis_exp_words(int fmt, int64_t n) {
+    return frsz2_bits(fmt) ? nblocks_bs(n, frsz2_bs(fmt)) : 0;
 }
 
 /* Q(x): store one column.  Returns 1 if a non-finite value was met. */
@@ -259,7 +291,7 @@ int or_basis_encode(int fmt, const double* x, int64_t n, void* vals, uint32_t* e
             if ((o[i] & 0x7C00u) == 0x7C00u) bad = 1;
         }
     } else {
-        bad = or_frsz2_encode(x, n, frsz2_bits(fmt), exps, (uint32_t*)vals);
+        bad = or_frsz2_encode_bs(x, n, frsz2_bits(fmt), frsz2_bs(fmt), exps, (uint32_t*)vals);
     }
     return bad;
 }
@@ -273,7 +305,7 @@ void or_basis_decode(int fmt, const void* vals, const uint32_t* exps, int64_t n,
     } else if (fmt == OR_F16) {
         for (int64_t i = 0; i < n; ++i) x[i] = or_f64_from_f16(((const uint16_t*)vals)[i]);
     } else {
-        or_frsz2_decode(exps, (const uint32_t*)vals, n, frsz2_bits(fmt), x);
+        or_frsz2_decode_bs(exps, (const uint32_t*)vals, n, frsz2_bits(fmt), frsz2_bs(fmt), x);
     }
 }
 

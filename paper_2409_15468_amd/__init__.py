@@ -166,22 +166,41 @@ def _check(st: int, where: str) -> int:
 
 
 CB_FRSZ2_GENERIC_BASE = 64
+CB_FRSZ2_B64_GENERIC_BASE = 128
+CB_FRSZ2_16_B64, CB_FRSZ2_32_B64 = 6, 7
+FORMATS_B64 = {"frsz2b64_16": CB_FRSZ2_16_B64, "frsz2b64_32": CB_FRSZ2_32_B64}
 
 
-def frsz2_bits_format(l: int) -> int:
-    """CB_FRSZ2_BITS(l): FRSZ2 with l bits (3 <= l <= 32) on the generic codec."""
-    if not 3 <= l <= 32:
-        raise ValueError("l must lie in [3, 32]")
-    return CB_FRSZ2_GENERIC_BASE + l
+def frsz2_bits_format(l: int, block: int = 32) -> int:
+    """CB_FRSZ2_BITS(l) (block 32) or CB_FRSZ2_B64_BITS(l) (block 64): FRSZ2
+    with l bits (3 <= l <= 32) on the generic codec."""
+    if not 3 <= l <= 32 or block not in (32, 64):
+        raise ValueError("l must lie in [3, 32] and the block size be 32 or 64")
+    return (CB_FRSZ2_GENERIC_BASE if block == 32 else CB_FRSZ2_B64_GENERIC_BASE) + l
+
+
+def format_bits(f: int) -> int:
+    """FRSZ2 l of format number f (0 for the float formats)."""
+    return {3: 16, 4: 21, 5: 32, 6: 16, 7: 32}.get(f, f & 63 if f > 64 else 0)
+
+
+def format_block(f: int) -> int:
+    """FRSZ2 block size of format number f (32 for the float formats)."""
+    return 64 if f in (6, 7) or f > CB_FRSZ2_B64_GENERIC_BASE else 32
 
 
 def _fmt(fmt) -> int:
-    """A format name or number: the six names of FORMATS, "frsz2_<l>" for any
-    other l in [3, 32], "frsz2g_<l>" for the generic codec at any l."""
+    """A format name or number: the names of FORMATS and FORMATS_B64,
+    "frsz2_<l>" for any other l in [3, 32], "frsz2g_<l>" for the generic codec
+    at any l; "frsz2b64_<l>" / "frsz2b64g_<l>" likewise with blocks of 64."""
     if not isinstance(fmt, str):
         return int(fmt)
     if fmt in FORMATS:
         return FORMATS[fmt]
+    if fmt in FORMATS_B64:
+        return FORMATS_B64[fmt]
+    if fmt.startswith("frsz2b64_") or fmt.startswith("frsz2b64g_"):
+        return frsz2_bits_format(int(fmt.split("_")[1]), 64)
     if fmt.startswith("frsz2_") or fmt.startswith("frsz2g_"):
         return frsz2_bits_format(int(fmt.split("_")[1]))
     raise KeyError(fmt)
@@ -283,9 +302,10 @@ class Basis:
         return cb_basis_column_bytes(self.fmt, self.n)
 
     def column_data_bytes(self) -> int:
-        nb = (self.n + 31) // 32
-        bits = {3: 16, 4: 21, 5: 32}.get(self.fmt, self.fmt - CB_FRSZ2_GENERIC_BASE if self.fmt > 5 else 0)
-        return nb * bits * 4 if bits else nb * 32 * (8, 4, 2)[self.fmt]
+        bits, bs = format_bits(self.fmt), format_block(self.fmt)
+        if not bits:
+            return (self.n + 31) // 32 * 32 * (8, 4, 2)[self.fmt]
+        return (self.n + bs - 1) // bs * (bs // 32) * bits * 4
 
     def column(self, c: int):
         """The stored bytes of column c (without the stride padding)."""

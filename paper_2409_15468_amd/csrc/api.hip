@@ -31,10 +31,8 @@ int64_t column_data_bytes(int f, int64_t n) {
     case CB_F64: return nb * 32 * 8;
     case CB_F32: return nb * 32 * 4;
     case CB_F16: return nb * 32 * 2;
-    case CB_FRSZ2_16:
-    case CB_FRSZ2_21:
-    case CB_FRSZ2_32: return nb * frsz2_bits_of(f) * 4;
-    default: return generic_format(f) ? nb * frsz2_bits_of(f) * 4 : -1;
+    default:  // frsz2: l words per 32 rows of the padded column
+        return valid_format(f) ? padded_rows_of(f, n) / 32 * frsz2_bits_of(f) * 4 : -1;
     }
 }
 
@@ -45,7 +43,7 @@ int64_t column_bytes(int f, int64_t n) {
     return d < 0 ? d : (d + 255) / 256 * 256;
 }
 
-int64_t exponent_words(int f, int64_t n) { return frsz2_bits_of(f) ? nblocks(n) : 0; }
+int64_t exponent_words(int f, int64_t n) { return frsz2_bits_of(f) ? padded_rows_of(f, n) >> block_log_of(f) : 0; }
 
 // Workspace of the primitives: a header holding the ticket counters of the
 // last-workgroup reduction, then the partial sums.

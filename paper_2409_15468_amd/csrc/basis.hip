@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
                                                     uint32_t* __restrict__ exps, int n, int np,
                                                     const double* w, const double* __restrict__ divisor,
                                                     double* v_out, int32_t* __restrict__ flag,
-                                                    const int* __restrict__ guard, int bits) {
+                                                    const int* __restrict__ guard, int bits, int bs_log) {
     if (guard && ld_ctl(guard) == 0) return;
     const int lane = threadIdx.x & 63;
     const int tile0 = blockIdx.x * kRowsPerWG + (threadIdx.x >> 6) * kTile;
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;  // IEEE division per entry
     }
     if (v_out) store_rows<FMT>(v_out, tile0, lane, n, v);
-    const bool bad = encode_tile<FMT>(values, exps, np, tile0, lane, v, bits);
+    const bool bad = encode_tile<FMT>(values, exps, np, tile0, lane, v, bits, bs_log);
     if (flag && bad) atomicOr(flag, 1);
 }
 
@@ -254,6 +254,8 @@ __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
     case CB_FRSZ2_16: { constexpr int F = CB_FRSZ2_16; KERNEL_CALL; break; } \
     case CB_FRSZ2_21: { constexpr int F = CB_FRSZ2_21; KERNEL_CALL; break; } \
     case CB_FRSZ2_GEN: { constexpr int F = CB_FRSZ2_GEN; KERNEL_CALL; break; } \
+    case CB_FRSZ2_16_B64: { constexpr int F = CB_FRSZ2_16_B64; KERNEL_CALL; break; } \
+    case CB_FRSZ2_32_B64: { constexpr int F = CB_FRSZ2_32_B64; KERNEL_CALL; break; } \
     default: { constexpr int F = CB_FRSZ2_32; KERNEL_CALL; break; }          \
     }
 
@@ -282,7 +284,7 @@ void launch_store(int fmt, const cb_basis& V, int col, const double* w, const do
     uint32_t* ex = V.exps ? V.exps + (int64_t)col * b.exp_stride : nullptr;
     dim3 grid((unsigned)row_groups(V.n));
     CB_DISPATCH(fmt, (k_store<F><<<grid, kThreads, 0, s>>>(vals, ex, b.n, b.np, w, divisor, v_out,
-                                                           flag, guard, b.bits)));
+                                                           flag, guard, b.bits, b.bs_log)));
 }
 
 void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s) {

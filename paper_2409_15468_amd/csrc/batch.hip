@@ -409,9 +409,7 @@ int32_t cbgmres_batch_max_n(void) { return kBatchMaxN; }
 int32_t cbgmres_batch_max_restart(void) { return kBatchMaxRestart; }
 
 int64_t cbgmres_batch_workspace_bytes(int32_t n, int32_t m, int format) {
-    if (n < 1 || n > kBatchMaxN || m < 1 || m > kBatchMaxRestart || !valid_format(format) ||
-        generic_format(format))
-        return -1;
+    if (n < 1 || n > kBatchMaxN || m < 1 || m > kBatchMaxRestart || !batch_format(format)) return -1;
     return batch_workspace_bytes(n, m, format);
 }
 
@@ -432,9 +430,9 @@ int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_opti
         if (q.m < 1 || q.m > kBatchMaxRestart)
             return fail(CB_ERR_INVALID_ARG, "batch item %d: m=%d out of range [1, %d]", i, q.m,
                         kBatchMaxRestart);
-        if (!(q.tol > 0.0) || !std::isfinite(q.tol) || !valid_format(q.format) || generic_format(q.format))
-            return fail(CB_ERR_INVALID_ARG, "batch item %d: bad tol or format (generic-l FRSZ2 formats "
-                        "run through cbgmres_solve)", i);
+        if (!(q.tol > 0.0) || !std::isfinite(q.tol) || !batch_format(q.format))
+            return fail(CB_ERR_INVALID_ARG, "batch item %d: bad tol or format (the generic-l and block-64 "
+                        "FRSZ2 formats run through cbgmres_solve)", i);
         if ((reinterpret_cast<uintptr_t>(q.workspace) & 255) != 0)
             return fail(CB_ERR_WORKSPACE, "batch item %d: workspace not 256-byte aligned", i);
         if ((int64_t)q.workspace_bytes < batch_workspace_bytes(q.A.n, q.m, q.format))

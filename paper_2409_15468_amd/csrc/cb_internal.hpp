@@ -44,17 +44,31 @@ __host__ __device__ inline int row_groups_dev(int np) { return (np + kRowsPerWG 
 constexpr int kProjectGroups = 1024;
 inline int project_groups(int64_t n) { int g = row_groups(n); return g < kProjectGroups ? g : kProjectGroups; }
 
-// Kernel template id of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l));
-// the bit count travels in BasisView::bits.
-constexpr int CB_FRSZ2_GEN = 6;
-inline bool generic_format(int f) { return f >= CB_FRSZ2_BITS(3) && f <= CB_FRSZ2_BITS(32); }
-inline bool valid_format(int f) { return (f >= CB_F64 && f <= CB_FRSZ2_32) || generic_format(f); }
+// Kernel template id of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l)
+// and CB_FRSZ2_B64_BITS(l)); l and the block size travel in BasisView.
+constexpr int CB_FRSZ2_GEN = 15;
+inline bool generic_b64(int f) { return f >= CB_FRSZ2_B64_BITS(3) && f <= CB_FRSZ2_B64_BITS(32); }
+inline bool generic_format(int f) {
+    return (f >= CB_FRSZ2_BITS(3) && f <= CB_FRSZ2_BITS(32)) || generic_b64(f);
+}
+inline bool valid_format(int f) { return (f >= CB_F64 && f <= CB_FRSZ2_32_B64) || generic_format(f); }
+// formats the one-workgroup batched solver runs (the paper's block size 32)
+inline bool batch_format(int f) { return f >= CB_F64 && f <= CB_FRSZ2_32; }
 inline int frsz2_bits_of(int f) {
-    return f == CB_FRSZ2_16 ? 16 : f == CB_FRSZ2_21 ? 21 : f == CB_FRSZ2_32 ? 32
+    return f == CB_FRSZ2_16 || f == CB_FRSZ2_16_B64 ? 16 : f == CB_FRSZ2_21 ? 21
+         : f == CB_FRSZ2_32 || f == CB_FRSZ2_32_B64 ? 32
+         : generic_b64(f) ? f - CB_FRSZ2_B64_GENERIC_BASE
          : generic_format(f) ? f - CB_FRSZ2_GENERIC_BASE : 0;
 }
+// log2 of the FRSZ2 block size (5 for float formats: rows are padded to 32)
+inline int block_log_of(int f) { return f == CB_FRSZ2_16_B64 || f == CB_FRSZ2_32_B64 || generic_b64(f) ? 6 : 5; }
 // the template instance that runs format f
 inline int kernel_format(int f) { return generic_format(f) ? CB_FRSZ2_GEN : f; }
+// rows a basis column of format f stores: n rounded up to its block size
+inline int64_t padded_rows_of(int f, int64_t n) {
+    const int64_t bs = int64_t(1) << block_log_of(f);
+    return (n + bs - 1) / bs * bs;
+}
 int64_t column_bytes(int f, int64_t n);       // column stride (256-byte multiple)
 int64_t column_data_bytes(int f, int64_t n);  // bytes of one column's values
 int64_t exponent_words(int f, int64_t n);
@@ -66,8 +80,9 @@ struct BasisView {
     int64_t col_bytes;
     int64_t exp_stride;  // exponent words per column
     int32_t n;
-    int32_t np;          // 32 * ceil(n/32)
+    int32_t np;          // rows stored: n rounded up to the block size
     int32_t bits;        // FRSZ2 l (0 for float formats)
+    int32_t bs_log;      // log2 of the FRSZ2 block size (5 or 6)
 };
 inline BasisView view_of(const cb_basis& V) {
     BasisView b;
@@ -76,8 +91,9 @@ inline BasisView view_of(const cb_basis& V) {
     b.col_bytes = column_bytes(V.format, V.n);
     b.exp_stride = exponent_words(V.format, V.n);
     b.n = V.n;
-    b.np = (int32_t)padded_rows(V.n);
+    b.np = (int32_t)padded_rows_of(V.format, V.n);
     b.bits = frsz2_bits_of(V.format);
+    b.bs_log = block_log_of(V.format);
     return b;
 }
 

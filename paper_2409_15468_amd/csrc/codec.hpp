@@ -104,7 +104,7 @@ template <int FMT>
 struct Map {
     // rows of lane t: 8 values in NG groups of GS consecutive rows, group k
     // starting at k * GSTRIDE + GS * t (relative to the tile)
-    static constexpr int GS = FMT == CB_F64 ? 2 : (FMT == CB_F32 || FMT == CB_FRSZ2_32) ? 4 : 8;
+    static constexpr int GS = FMT == CB_F64 ? 2 : (FMT == CB_F32 || FMT == CB_FRSZ2_32 || FMT == CB_FRSZ2_32_B64) ? 4 : 8;
     static constexpr int NG = 8 / GS;
     static constexpr int GSTRIDE = 64 * GS;
     __device__ static int row(int t, int q) { return (q / GS) * GSTRIDE + GS * t + (q % GS); }
@@ -210,8 +210,10 @@ template <> struct Tile<CB_F16> : FloatTile<CB_F16> {};
 
 __device__ __forceinline__ int scale_exp(uint32_t E, int L) { return (E ? (int)E : 1) - 1023 - (L - 2); }
 
-template <>
-struct Tile<CB_FRSZ2_32> {
+// frsz2_32 with blocks of 2^LOGBS values: code q is word q of the block, so
+// row r's code is word r of the column whatever the block size.
+template <int LOGBS>
+struct Frsz2Tile32 {
     using M = Map<CB_FRSZ2_32>;
     uint4 x[2];
     uint32_t e[2];
@@ -224,7 +226,7 @@ struct Tile<CB_FRSZ2_32> {
             const int r = tile0 + M::group_row(lane, k);
             const bool live = (LM & kFull) || r < V.np;
             x[k] = live ? ld16<(LM & kStream) != 0>(base + (int64_t)r * 4) : make_uint4(0, 0, 0, 0);
-            e[k] = live ? ex[r >> 5] : 0u;
+            e[k] = live ? ex[r >> LOGBS] : 0u;
         }
     }
     __device__ __forceinline__ double m(int q) const {
@@ -255,9 +257,12 @@ struct Tile<CB_FRSZ2_32> {
         for (int q = 0; q < 8; ++q) out[q] = ldexp(m(q), scale_exp(e[q >> 2], 32));
     }
 };
+template <> struct Tile<CB_FRSZ2_32> : Frsz2Tile32<5> {};
+template <> struct Tile<CB_FRSZ2_32_B64> : Frsz2Tile32<6> {};
 
-template <>
-struct Tile<CB_FRSZ2_16> {
+// frsz2_16 with blocks of 2^LOGBS values: row r's code is half-word r.
+template <int LOGBS>
+struct Frsz2Tile16 {
     using M = Map<CB_FRSZ2_16>;
     uint4 x;
     uint32_t e;
@@ -267,7 +272,7 @@ struct Tile<CB_FRSZ2_16> {
         const int r = tile0 + M::group_row(lane, 0);
         const bool live = (LM & kFull) || r < V.np;
         x = live ? ld16<(LM & kStream) != 0>(base + (int64_t)r * 2) : make_uint4(0, 0, 0, 0);
-        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
+        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> LOGBS)] : 0u;
     }
     __device__ __forceinline__ double m(int q) const {
         uint32_t wd = word_of(x, q >> 1);
@@ -291,6 +296,8 @@ struct Tile<CB_FRSZ2_16> {
         for (int q = 0; q < 8; ++q) out[q] = ldexp(m(q), se);
     }
 };
+template <> struct Tile<CB_FRSZ2_16> : Frsz2Tile16<5> {};
+template <> struct Tile<CB_FRSZ2_16_B64> : Frsz2Tile16<6> {};
 
 // frsz2_21.  The lane's 8 values 8t .. 8t+7 are codes 8s .. 8s+7 (s = t % 4)
 // of block t / 4 of the tile; they start at bit 168 s = 32 (5 s) + 8 s of the
@@ -352,12 +359,13 @@ struct Tile<CB_FRSZ2_21> {
     }
 };
 
-// Any l in [3, 32] (the generic formats).  Lane t owns rows 8t .. 8t+7, i.e.
-// codes 8s .. 8s+7 (s = t % 4) of block t / 4, which start at bit 8 s l of the
-// block's l words: word 8 s l / 32, bit 8 s l % 32 of it.  The lane loads the
-// (at most 9) words that hold its 8 codes and walks them with a two-word
-// window that advances by one word whenever the bit position passes 32; the
-// window shifts use fixed register indices, so nothing spills.
+// Any l in [3, 32] (the generic formats), blocks of 32 or 64 values.  Lane t
+// owns rows 8t .. 8t+7, i.e. codes 8s .. 8s+7 (s = t mod P, P = 4 or 8 lanes
+// per block) of block t / P, which start at bit 8 s l of the block's words:
+// word 8 s l / 32, bit 8 s l % 32 of it.  The lane loads the (at most 9) words
+// that hold its 8 codes and walks them with a two-word window that advances
+// by one word whenever the bit position passes 32; the window shifts use
+// fixed register indices, so nothing spills.
 template <>
 struct Tile<CB_FRSZ2_GEN> {
     uint32_t y[9];
@@ -367,17 +375,18 @@ struct Tile<CB_FRSZ2_GEN> {
     template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
         L = V.bits;
+        const int lb = V.bs_log;
         const uint32_t* base = reinterpret_cast<const uint32_t*>(V.values + (int64_t)col * V.col_bytes);
         const int r = tile0 + 8 * lane;
         const bool live = (LM & kFull) || r < V.np;
-        const uint32_t start = 8u * (uint32_t)(lane & 3) * (uint32_t)L;
+        const uint32_t start = 8u * (uint32_t)(lane & ((1 << (lb - 3)) - 1)) * (uint32_t)L;
         off = start & 31u;
-        // the codes end at bit start + 8 l - 1 <= 32 l - 1: inside the block
+        // the codes end at bit start + 8 l - 1 <= 2^lb l - 1: inside the block
         const int nw = (int)((off + 8u * (uint32_t)L + 31u) >> 5);
-        const uint32_t* p = base + (int64_t)(r >> 5) * L + (start >> 5);
+        const uint32_t* p = base + (int64_t)(r >> lb) * (L << (lb - 5)) + (start >> 5);
 #pragma unroll
         for (int k = 0; k < 9; ++k) y[k] = (live && k < nw) ? ld4<(LM & kStream) != 0>(p + k) : 0u;
-        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
+        e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> lb)] : 0u;
     }
     __device__ __forceinline__ void codes(uint32_t* c) const {
         uint32_t w[9];
@@ -464,12 +473,14 @@ __device__ __forceinline__ uint32_t frsz2_code_rt(double v, uint32_t E, int L) {
 
 __device__ __forceinline__ uint32_t exp_field(double v) { return (hi32(v) >> 20) & 0x7FFu; }
 
-// max over lane groups of 2^LOG lanes (LOG <= 3) with DPP moves inside rows
+// max over lane groups of 2^LOG lanes (LOG <= 4) with DPP moves inside rows
+// (quad swaps, then the half-row and row mirrors)
 template <int LOG>
 __device__ __forceinline__ uint32_t group_max(uint32_t x) {
     if constexpr (LOG >= 1) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));
     if constexpr (LOG >= 2) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));
     if constexpr (LOG >= 3) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false));
+    if constexpr (LOG >= 4) x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false));
     return x;
 }
 

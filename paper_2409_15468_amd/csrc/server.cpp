@@ -74,10 +74,10 @@ constexpr int32_t kSmallN = 16384;
 constexpr int kMaxBatch = 512;
 constexpr int kBatchLanes = 2;
 
-// The batched solver runs the fixed formats only; generic-l FRSZ2 requests go
-// to the solve lanes whatever their size.
+// The batched solver runs the block-32 fixed formats only; other FRSZ2
+// requests go to the solve lanes whatever their size.
 static bool is_small(int32_t n, int32_t m, int format) {
-    return n <= kSmallN && m <= kBatchMaxRestart && !generic_format(format);
+    return n <= kSmallN && m <= kBatchMaxRestart && batch_format(format);
 }
 
 static int64_t al256(int64_t x) { return (x + 255) & ~int64_t(255); }

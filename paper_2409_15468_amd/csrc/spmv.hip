@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
                                                     const double* __restrict__ divisor, double* __restrict__ y,
                                                     double* __restrict__ partials, unsigned char* __restrict__ values,
                                                     uint32_t* __restrict__ exps, int32_t* __restrict__ flag,
-                                                    const int* __restrict__ guard, int bits) {
+                                                    const int* __restrict__ guard, int bits, int bs_log) {
     if (guard && ld_ctl(guard) == 0) return;
     const double d = ld_ctl(divisor);
     const int lane = threadIdx.x & 63;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
         load_rows<FMT>(w, tile0, lane, n, v);
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;
-        bad |= encode_tile<FMT>(values, exps, np, tile0, lane, v, bits);
+        bad |= encode_tile<FMT>(values, exps, np, tile0, lane, v, bits, bs_log);
     }
     if (bad) atomicOr(flag, 1);
     double nrm;
@@ -255,7 +255,7 @@ void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, con
 #define CB_SS_CASE(F)                                                                                  \
     case F:                                                                                            \
         k_spmv_store<F><<<G, 256, 0, s>>>(A.n, b.np, A.row_ptr, A.col, A.val, lpr, w, divisor, y,      \
-                                          partials, vals, ex, flag, guard, b.bits);                    \
+                                          partials, vals, ex, flag, guard, b.bits, b.bs_log);          \
         break;
     switch (kernel_format(fmt)) {
         CB_SS_CASE(CB_F64)
@@ -264,6 +264,8 @@ void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, con
         CB_SS_CASE(CB_FRSZ2_16)
         CB_SS_CASE(CB_FRSZ2_21)
         CB_SS_CASE(CB_FRSZ2_GEN)
+        CB_SS_CASE(CB_FRSZ2_16_B64)
+        CB_SS_CASE(CB_FRSZ2_32_B64)
         default:
         CB_SS_CASE(CB_FRSZ2_32)
     }

@@ -18,10 +18,12 @@ namespace dev {
 // float16; float64 stored as is).  Groups of rows at or past np are not
 // written.  Returns true if a stored value is not finite (for frsz2: a block
 // whose exponent field is 2047).
-// bits: l of the generic FRSZ2 formats (ignored by the others).
+// bits, bs_log: l and log2 of the block size of the generic FRSZ2 formats
+// (ignored by the others).
 template <int FMT>
 __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, uint32_t* __restrict__ exps,
-                                            int np, int tile0, int lane, const double* v, int bits = 0) {
+                                            int np, int tile0, int lane, const double* v, int bits = 0,
+                                            int bs_log = 5) {
     using M = Map<FMT>;
     bool bad = false;
     if constexpr (FMT == CB_F64 || FMT == CB_F32 || FMT == CB_F16) {
@@ -54,29 +56,35 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
             constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
             if (r < np) *reinterpret_cast<uint4*>(values + (int64_t)r * esz) = o;
         }
-    } else if constexpr (FMT == CB_FRSZ2_32) {
-        // groups of 4 values; the 8 lanes 8u..8u+7 hold one block
+    } else if constexpr (FMT == CB_FRSZ2_32 || FMT == CB_FRSZ2_32_B64) {
+        // groups of 4 values; the 8 lanes 8u..8u+7 hold one block of 32 (the
+        // 16 lanes 16u..16u+15 one block of 64)
+        constexpr int LB = FMT == CB_FRSZ2_32 ? 5 : 6;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int r = tile0 + M::group_row(lane, k);
             uint32_t E = max(max(exp_field(v[4 * k]), exp_field(v[4 * k + 1])),
                              max(exp_field(v[4 * k + 2]), exp_field(v[4 * k + 3])));
-            E = group_max<3>(E);  // step 1: block maximum
+            E = group_max<LB - 2>(E);  // step 1: block maximum
             uint4 o = make_uint4(frsz2_code<32>(v[4 * k], E), frsz2_code<32>(v[4 * k + 1], E),
                                  frsz2_code<32>(v[4 * k + 2], E), frsz2_code<32>(v[4 * k + 3], E));
             if (r < np) {
                 *reinterpret_cast<uint4*>(values + (int64_t)r * 4) = o;
-                if ((lane & 7) == 0) exps[r >> 5] = E;
+                if ((lane & ((1 << (LB - 2)) - 1)) == 0) exps[r >> LB] = E;
             }
             bad |= E == 0x7FFu;
         }
     } else {
-        // 8 values per lane; the 4 lanes 4u..4u+3 hold one block
+        // 8 values per lane; the 4 lanes 4u..4u+3 hold one block of 32 (the
+        // 8 lanes 8u..8u+7 one block of 64)
+        const int lb = FMT == CB_FRSZ2_GEN ? bs_log : FMT == CB_FRSZ2_16_B64 ? 6 : 5;
         const int r = tile0 + 8 * lane;
         uint32_t E = 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) E = max(E, exp_field(v[q]));
         E = group_max<2>(E);
+        if (lb == 6) E = max(E, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)E, 0x141, 0xF, 0xF, false));
+        const bool first = (lane & ((1 << (lb - 3)) - 1)) == 0;  // the block's first lane
         bad = E == 0x7FFu;
         if constexpr (FMT == CB_FRSZ2_GEN) {
             // The lane's 8 codes go to bits 8 s l .. 8 s l + 8 l - 1 of its
@@ -89,9 +97,9 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
             uint32_t c[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) c[q] = frsz2_code_rt(v[q], E, L);
-            const uint32_t start = 8u * (uint32_t)(lane & 3) * (uint32_t)L;
+            const uint32_t start = 8u * (uint32_t)(lane & ((1 << (lb - 3)) - 1)) * (uint32_t)L;
             const uint32_t off = start & 31u;
-            uint32_t* blk = reinterpret_cast<uint32_t*>(values) + (int64_t)(r >> 5) * L + (start >> 5);
+            uint32_t* blk = reinterpret_cast<uint32_t*>(values) + (int64_t)(r >> lb) * (L << (lb - 5)) + (start >> 5);
             const bool live = r < np;
             uint64_t acc = 0;
             uint32_t nb = off, head = 0;
@@ -109,19 +117,20 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
                     nb -= 32u;
                 }
             }
-            const uint32_t next_head = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)head, 0xF9, 0xF, 0xF, false);
+            // the next lane's first word (row shift by one lane: crosses quads)
+            const uint32_t next_head = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)head, 0x101, 0xF, 0xF, false);
             if (live) {
                 if (nb > 0u) blk[wi] = (uint32_t)acc | next_head;
-                if ((lane & 3) == 0) exps[r >> 5] = E;
+                if (first) exps[r >> lb] = E;
             }
-        } else if constexpr (FMT == CB_FRSZ2_16) {
+        } else if constexpr (FMT == CB_FRSZ2_16 || FMT == CB_FRSZ2_16_B64) {
             uint32_t c[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) c[q] = frsz2_code<16>(v[q], E);
             if (r < np) {
                 *reinterpret_cast<uint4*>(values + (int64_t)r * 2) =
                     make_uint4(c[0] | c[1] << 16, c[2] | c[3] << 16, c[4] | c[5] << 16, c[6] | c[7] << 16);
-                if ((lane & 3) == 0) exps[r >> 5] = E;
+                if (first) exps[r >> lb] = E;
             }
         } else {
             uint32_t c[8];

@@ -83,7 +83,7 @@ def test_argument_errors_without_device_work():
     assert st == cb.CB_ERR_INVALID_ARG
     V = cb.cb_basis(5, 100, 4, 0, None, None)
     assert L.cb_basis_load(C.byref(V), 0, None, None) == cb.CB_ERR_INVALID_ARG
-    V = cb.cb_basis(7, 100, 4, 0, 1, 1)
+    V = cb.cb_basis(9, 100, 4, 0, 1, 1)  # 9: no such format
     assert L.cb_basis_load(C.byref(V), 0, 1, None) == cb.CB_ERR_INVALID_ARG
     for s in range(10):
         assert L.cb_status_string(s)

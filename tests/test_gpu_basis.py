@@ -26,6 +26,8 @@ def u32(t):
 FORMATS = list(oracle.FORMATS)
 # generic-codec widths (frsz2g_32: the generic codec at l = 32)
 GENERIC = ["frsz2_3", "frsz2_7", "frsz2_12", "frsz2_27", "frsz2g_32"]
+# blocks of 64 values: the specialised l = 16, 32 and the generic codec
+B64 = ["frsz2b64_16", "frsz2b64_32", "frsz2b64_21", "frsz2b64_5"]
 
 
 def build_basis(fmt, n, j, seed):
@@ -44,7 +46,7 @@ def build_basis(fmt, n, j, seed):
     return V, enc, dec
 
 
-@pytest.mark.parametrize("fmt", FORMATS + GENERIC)
+@pytest.mark.parametrize("fmt", FORMATS + GENERIC + B64)
 @pytest.mark.parametrize("n", [777, 4101, 2048 * 5 + 13])
 def test_store_bit_exact_with_division(fmt, n):
     w = mixed_vector(n, seed=n, spread=4)
@@ -77,7 +79,7 @@ def test_store_float16_overflow_flag():
     assert int(flag.item()) == 1
 
 
-@pytest.mark.parametrize("fmt", FORMATS + GENERIC)
+@pytest.mark.parametrize("fmt", FORMATS + GENERIC + B64)
 @pytest.mark.parametrize("n,j", [(777, 1), (4101, 5), (2048 * 5 + 13, 17), (3000, 70)])
 def test_project_subtract_combine(fmt, n, j):
     V, enc, dec = build_basis(fmt, n, j, seed=n + j)

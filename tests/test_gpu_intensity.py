@@ -10,7 +10,8 @@ import paper_2409_15468_amd as cb
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-FORMATS = list(oracle.FORMATS) + ["frsz2_9", "frsz2_27"]  # the last two on the generic codec
+# frsz2_9, frsz2_27: the generic codec; frsz2b64_*: blocks of 64 values
+FORMATS = list(oracle.FORMATS) + ["frsz2_9", "frsz2_27", "frsz2b64_16", "frsz2b64_32", "frsz2b64_21"]
 
 
 @pytest.mark.parametrize("fmt", FORMATS)

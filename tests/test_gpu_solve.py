@@ -207,3 +207,28 @@ def test_generic_codec_solve_is_the_specialised_solve(l):
     r2, x2, h2 = gpu_solve(s.A, s.b, 30, 1e-10, f"frsz2g_{l}", history_cap=2000)
     assert r1["iterations"] == r2["iterations"] and r1["reorths"] == r2["reorths"]
     assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64)) and np.array_equal(h1, h2)
+
+
+@pytest.mark.parametrize("fmt", ["frsz2b64_16", "frsz2b64_32", "frsz2b64_21"])
+def test_block64_solves(fmt):
+    """Blocks of 64 values on the plain configuration: tolerance met on the
+    host, iterations within 2% of the oracle's with the same block size (or,
+    for the 16-bit code, within the oracle's spread under last-bit
+    perturbations of b), the first cycle's history alongside."""
+    s = synth.plain_2d(N=64, seed=0)
+    res, x, hist = gpu_solve(s.A, s.b, 50, 1e-10, fmt, history_cap=5000)
+    ref = oracle.gmres(s.A, s.b, 50, 1e-10, fmt, hist_cap=5000)
+    print(f"{fmt}: gpu {res['iterations']} oracle {ref.iterations}")
+    assert res["status"] == 0 and res["converged"]
+    assert host_rrn(s.A, s.b, x) <= 1e-10 * (1 + 1e-6)
+    if fmt == "frsz2b64_16" and not within_2pct(res["iterations"], ref.iterations):
+        rng = np.random.default_rng(0)
+        spread = [oracle.gmres(s.A, s.b * (1 + 2.0 ** -52 * rng.choice([-1.0, 0.0, 1.0], s.A.n)), 50, 1e-10,
+                               fmt).iterations for _ in range(6)] + [ref.iterations]
+        print(f"{fmt} oracle spread: {sorted(spread)}")
+        assert 0.98 * min(spread) <= res["iterations"] <= 1.02 * max(spread)
+    else:
+        assert within_2pct(res["iterations"], ref.iterations), (res["iterations"], ref.iterations)
+    l = int(fmt.split("_")[1])
+    k = min(40, hist.size, ref.history.size)
+    np.testing.assert_allclose(hist[:k], ref.history[:k], rtol=max(1e-6, 64 * 2.0 ** -(l - 2)))

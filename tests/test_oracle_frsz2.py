@@ -331,3 +331,70 @@ def test_basis_formats_match_numpy_casts():
         assert np.all(full[small.size:] == 0)
     # float16 overflow is reported as non-finite
     assert oracle.basis_encode("float16", np.array([1.0, 7e4]))[2]
+
+
+# ---------------------------------------------------------------- blocks of 64 values
+def grid_codes_bs(block, l, bs):
+    """grid_codes for a block of bs values (tail padded with +0.0)."""
+    bl = [_bits(float(v)) for v in block] + [0] * (bs - len(block))
+    E = max((b >> 52) & 0x7FF for b in bl)
+    Eeff = max(E, 1)
+    codes = []
+    for b in bl:
+        s, e, f = b >> 63, (b >> 52) & 0x7FF, b & ((1 << 52) - 1)
+        sig = ((1 << 52) | f) if e else f
+        sh = max(e, 1) - 1075 - Eeff + 1023 + l - 2
+        mag = sig << sh if sh >= 0 else sig >> (-sh)
+        codes.append((s << (l - 1)) | mag)
+    return E, codes
+
+
+def pack_lsb_first_n(codes, l):
+    bitstr = np.zeros(len(codes) * l, np.uint8)
+    for q, c in enumerate(codes):
+        for t in range(l):
+            bitstr[q * l + t] = (c >> t) & 1
+    return np.packbits(bitstr, bitorder="little").view("<u4")
+
+
+@pytest.mark.parametrize("l", [5, 16, 21, 32])
+def test_block64_matches_grid_definition_and_packer(l):
+    """Blocks of 64 values share one exponent: codes by the value definition
+    on the 64-value block, packed LSB first into 2 l words; ragged tail."""
+    rng = np.random.default_rng(200 + l)
+    n = 64 * 9 + 23
+    x = _random_blocks(rng, (n + 31) // 32, 8)[:n]
+    exps, words, bad = oracle.frsz2_encode(x, l, bs=64)
+    assert not bad and exps.size == 10 and words.size == 10 * 2 * l
+    for b in range(10):
+        E, codes = grid_codes_bs(x[64 * b:64 * b + 64], l, 64)
+        assert int(exps[b]) == E
+        np.testing.assert_array_equal(words[b * 2 * l:(b + 1) * 2 * l], pack_lsb_first_n(codes, l))
+    d = oracle.frsz2_decode(exps, words, n, l, bs=64)
+    Eeff = np.maximum(np.repeat(exps.astype(np.int64), 64)[:n], 1)
+    u = np.ldexp(1.0, (Eeff - 1023 - (l - 2)).astype(np.int32))
+    err = np.abs(x) - np.abs(d)
+    assert np.all(err >= 0) and np.all(err < u) and np.all(np.signbit(d) == np.signbit(x))
+    one = np.array([oracle.frsz2_decode_value(exps, words, i, l, bs=64) for i in range(n)])
+    assert np.array_equal(one.view(np.uint64), d.view(np.uint64))
+
+
+@pytest.mark.parametrize("l", [7, 16, 32])
+def test_block64_is_two_blocks32_when_exponents_agree(l):
+    """When both halves of a 64-value block have the same largest exponent,
+    the 64-block's words are the two 32-blocks' words in sequence."""
+    rng = np.random.default_rng(l)
+    x = rng.uniform(-1, 1, 64 * 12)
+    x[::32] = 1.5  # every 32-value half holds a value of exponent field 1023
+    e64, w64, _ = oracle.frsz2_encode(x, l, bs=64)
+    e32, w32, _ = oracle.frsz2_encode(x, l)
+    np.testing.assert_array_equal(w64, w32)
+    np.testing.assert_array_equal(e64, e32[::2])
+    # halves with different maxima: the half with the smaller maximum is coarser
+    y = x.copy()
+    y[32:64] *= 2.0 ** -6
+    e, w, _ = oracle.frsz2_encode(y, l, bs=64)
+    d64 = oracle.frsz2_decode(e, w, y.size, l, bs=64)
+    ee, ww, _ = oracle.frsz2_encode(y, l)
+    d32 = oracle.frsz2_decode(ee, ww, y.size, l)
+    assert np.all(np.abs(y[32:64] - d64[32:64]) >= np.abs(y[32:64] - d32[32:64]))
