@@ -23,6 +23,11 @@
  *    error no kernel has been enqueued and cb_last_error() (thread-local)
  *    describes the cause.
  *  - Sizes n are row counts (1 <= n < 2^31 - 32); indices are 32-bit.
+ *  - Alignment: basis values / FRSZ2 words and the FP64 vectors the basis
+ *    kernels read or write (w, x, v_out, a solve's x) are accessed in 16-byte
+ *    pieces and must be 16-byte aligned; other arrays need their element's
+ *    alignment.  Every hipMalloc (and torch) allocation is 256-byte aligned.
+ *    A misaligned pointer returns CB_ERR_INVALID_ARG.
  */
 #ifndef CBGMRES_H
 #define CBGMRES_H

@@ -73,6 +73,15 @@ static int check_basis(const cb_basis* V, int need_cols) {
     if (V->ncols < need_cols) return fail(CB_ERR_INVALID_ARG, "basis has %d columns, %d needed", V->ncols, need_cols);
     if (!V->values) return fail(CB_ERR_INVALID_ARG, "basis values pointer is NULL");
     if (frsz2_bits_of(V->format) && !V->exps) return fail(CB_ERR_INVALID_ARG, "frsz2 basis needs exps");
+    if (!aligned(V->values, 16) || !aligned(V->exps, 4))
+        return fail(CB_ERR_INVALID_ARG, "basis values must be 16-byte and exps 4-byte aligned");
+    return CB_OK;
+}
+
+// the FP64 vectors the row kernels read or write in 16-byte pairs
+static int check_vec16(const void* a, const void* b = nullptr, const void* c = nullptr) {
+    if (!aligned(a, 16) || !aligned(b, 16) || !aligned(c, 16))
+        return fail(CB_ERR_INVALID_ARG, "device vectors must be 16-byte aligned");
     return CB_OK;
 }
 
@@ -118,6 +127,8 @@ int frsz2_compress(const double* x, int64_t n, int bits, uint32_t* exps, uint32_
     if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (3 to 32)", bits);
     if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
     if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
+    if (int st = check_vec16(x, words)) return st;
+    if (!aligned(exps, 4)) return fail(CB_ERR_INVALID_ARG, "exps must be 4-byte aligned");
     cb_basis V{f, (int32_t)n, 1, 0, words, exps};
     int32_t* flag = nonfinite_flag;
     launch_store(f, V, 0, x, nullptr, nullptr, flag, nullptr, (hipStream_t)stream);
@@ -131,6 +142,8 @@ int frsz2_decompress(const uint32_t* exps, const uint32_t* words, int64_t n, int
     if (f < 0) return fail(CB_ERR_UNSUPPORTED_BITS, "frsz2 bits=%d (3 to 32)", bits);
     if (bad_n(n)) return fail(CB_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
     if (!x || !exps || !words) return fail(CB_ERR_INVALID_ARG, "NULL pointer");
+    if (int st = check_vec16(x, words)) return st;
+    if (!aligned(exps, 4)) return fail(CB_ERR_INVALID_ARG, "exps must be 4-byte aligned");
     cb_basis V{f, (int32_t)n, 1, 0, const_cast<uint32_t*>(words), const_cast<uint32_t*>(exps)};
     launch_load(f, V, 0, x, (hipStream_t)stream);
     CB_HIP(hipGetLastError());
@@ -151,6 +164,7 @@ int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double
                    double* v_out, int32_t* nonfinite_flag, void* stream) {
     if (int st = check_basis(V, col + 1)) return st;
     if (col < 0 || !w) return fail(CB_ERR_INVALID_ARG, "bad column or NULL w");
+    if (int st = check_vec16(w, v_out)) return st;
     launch_store(V->format, *V, col, w, divisor, v_out, nonfinite_flag, nullptr, (hipStream_t)stream);
     CB_HIP(hipGetLastError());
     return CB_OK;
@@ -159,6 +173,7 @@ int cb_basis_store(const cb_basis* V, int32_t col, const double* w, const double
 int cb_basis_load(const cb_basis* V, int32_t col, double* x, void* stream) {
     if (int st = check_basis(V, col + 1)) return st;
     if (col < 0 || !x) return fail(CB_ERR_INVALID_ARG, "bad column or NULL x");
+    if (int st = check_vec16(x)) return st;
     launch_load(V->format, *V, col, x, (hipStream_t)stream);
     CB_HIP(hipGetLastError());
     return CB_OK;
@@ -173,6 +188,7 @@ int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, voi
                    size_t work_bytes, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !w || !h || !work) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (int st = check_vec16(w)) return st;
     if (j > kMaxRestart + 1)
         return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     if ((int64_t)work_bytes < reduce_workspace_bytes(V->n, j, 0))
@@ -189,6 +205,7 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
                     void* work, size_t work_bytes, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !w || !h) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (int st = check_vec16(w)) return st;
     if (j > kMaxRestart + 1)
         return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     if (norm2 && (!work || (int64_t)work_bytes < reduce_workspace_bytes(V->n, 1, 0)))
@@ -205,6 +222,7 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
 int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !y || !x) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (int st = check_vec16(x)) return st;
     if (j > kMaxRestart + 1)
         return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
     launch_subtract(V->format, *V, j, nullptr, y, x, nullptr, nullptr, +1, Epi{}, (hipStream_t)stream);

@@ -435,6 +435,8 @@ int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_opti
                         "FRSZ2 formats run through cbgmres_solve)", i);
         if ((reinterpret_cast<uintptr_t>(q.workspace) & 255) != 0)
             return fail(CB_ERR_WORKSPACE, "batch item %d: workspace not 256-byte aligned", i);
+        if (!aligned(q.x, 16) || !aligned(q.b, 8))
+            return fail(CB_ERR_INVALID_ARG, "batch item %d: x must be 16-byte and b 8-byte aligned", i);
         if ((int64_t)q.workspace_bytes < batch_workspace_bytes(q.A.n, q.m, q.format))
             return fail(CB_ERR_WORKSPACE, "batch item %d: workspace %zu < %lld bytes", i, q.workspace_bytes,
                         (long long)batch_workspace_bytes(q.A.n, q.m, q.format));

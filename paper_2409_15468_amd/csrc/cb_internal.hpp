@@ -23,6 +23,9 @@ int fail(int status, const char* fmt, ...);
                               hipGetErrorString(e_), __FILE__, __LINE__);                 \
     } while (0)
 
+// NULL counts as aligned (optional arguments)
+inline bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
 // ---------------------------------------------------------------- geometry
 constexpr int kBS = 32;           // FRSZ2 block size (values per shared exponent)
 constexpr int kSeg = 8;           // rows per thread in the row-segment kernels

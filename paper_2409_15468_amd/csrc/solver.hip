@@ -435,6 +435,7 @@ static int check_solve_args(const cb_csr* A, const double* b, const double* x, i
         return fail(CB_ERR_INVALID_ARG, "restart m=%d out of range [1, %d]", m, kMaxRestart);
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(CB_ERR_INVALID_ARG, "tol must be positive");
     if (!valid_format(format)) return fail(CB_ERR_INVALID_ARG, "unknown basis format %d", format);
+    if (!aligned(x, 16) || !aligned(b, 8)) return fail(CB_ERR_INVALID_ARG, "x must be 16-byte and b 8-byte aligned");
     return CB_OK;
 }
 

@@ -175,3 +175,30 @@ def test_precond_arguments_without_device_work():
     assert call(cb.CB_PRECOND_JACOBI, 256, ws_bytes=need - 1) == cb.CB_ERR_WORKSPACE
     assert L.cb_jacobi_setup(None, 256, None) == cb.CB_ERR_INVALID_ARG
     assert L.cb_jacobi_setup(C.byref(cb.cb_csr(0, 0, 256, None, None)), 256, None) == cb.CB_ERR_INVALID_ARG
+
+
+def test_misaligned_pointers_rejected_without_device_work():
+    """Basis values and the vectors the row kernels access in 16-byte pieces
+    must be 16-byte aligned; a misaligned pointer is an argument error, caught
+    before any launch.  Pointers here are never dereferenced."""
+    L = cb.lib()
+    V = cb.cb_basis(5, 1000, 4, 0, 256 + 8, 256)
+    assert L.cb_basis_load(C.byref(V), 0, 256, None) == cb.CB_ERR_INVALID_ARG
+    V = cb.cb_basis(5, 1000, 4, 0, 256, 258)
+    assert L.cb_basis_load(C.byref(V), 0, 256, None) == cb.CB_ERR_INVALID_ARG
+    V = cb.cb_basis(5, 1000, 4, 0, 256, 256)
+    assert L.cb_basis_load(C.byref(V), 0, 264, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_basis_store(C.byref(V), 0, 264, None, None, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_basis_store(C.byref(V), 0, 256, None, 264, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_project(C.byref(V), 2, 264, 256, 256, 1 << 30, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_subtract(C.byref(V), 2, 256, 264, None, None, 0, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_basis_combine(C.byref(V), 2, 256, 264, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_compress(264, 1000, 16, 256, 256, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_compress(256, 1000, 16, 256, 264, None, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_decompress(256, 264, 1000, 21, 256, None) == cb.CB_ERR_INVALID_ARG
+    A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    res = cb.cb_result()
+    assert L.cbgmres_solve(C.byref(A), 256, 264, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res),
+                           None) == cb.CB_ERR_INVALID_ARG
+    assert L.cbgmres_solve(C.byref(A), 260, 256, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res),
+                           None) == cb.CB_ERR_INVALID_ARG
