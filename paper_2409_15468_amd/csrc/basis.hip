@@ -81,12 +81,22 @@ __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
         double wv[8];
         load_rows<FMT>(w, tile0, lane, V.n, wv);
         const bool full = tile0 + kTile <= V.np;
-        if (stream) {
-            if (full) project_tile<FMT, kFull | kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
-            else project_tile<FMT, kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+        if constexpr (FMT == CB_FRSZ2_GENW) {  // 4 column tiles at a time: no spills, same sums
+            if (stream) {
+                if (full) project_tile_narrow<FMT, kFull | kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+                else project_tile_narrow<FMT, kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+            } else {
+                if (full) project_tile_narrow<FMT, kFull>(V, c0, c1, tile0, lane, wv, red[wave]);
+                else project_tile_narrow<FMT, 0>(V, c0, c1, tile0, lane, wv, red[wave]);
+            }
         } else {
-            if (full) project_tile<FMT, kFull>(V, c0, c1, tile0, lane, wv, red[wave]);
-            else project_tile<FMT, 0>(V, c0, c1, tile0, lane, wv, red[wave]);
+            if (stream) {
+                if (full) project_tile<FMT, kFull | kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+                else project_tile<FMT, kStream>(V, c0, c1, tile0, lane, wv, red[wave]);
+            } else {
+                if (full) project_tile<FMT, kFull>(V, c0, c1, tile0, lane, wv, red[wave]);
+                else project_tile<FMT, 0>(V, c0, c1, tile0, lane, wv, red[wave]);
+            }
         }
     }
     __syncthreads();
@@ -254,6 +264,7 @@ __global__ void k_fill(double* __restrict__ x, double v, int64_t n) {
     case CB_FRSZ2_16: { constexpr int F = CB_FRSZ2_16; KERNEL_CALL; break; } \
     case CB_FRSZ2_21: { constexpr int F = CB_FRSZ2_21; KERNEL_CALL; break; } \
     case CB_FRSZ2_GEN: { constexpr int F = CB_FRSZ2_GEN; KERNEL_CALL; break; } \
+    case CB_FRSZ2_GENW: { constexpr int F = CB_FRSZ2_GENW; KERNEL_CALL; break; } \
     case CB_FRSZ2_16_B64: { constexpr int F = CB_FRSZ2_16_B64; KERNEL_CALL; break; } \
     case CB_FRSZ2_32_B64: { constexpr int F = CB_FRSZ2_32_B64; KERNEL_CALL; break; } \
     default: { constexpr int F = CB_FRSZ2_32; KERNEL_CALL; break; }          \

@@ -47,9 +47,14 @@ __host__ __device__ inline int row_groups_dev(int np) { return (np + kRowsPerWG 
 constexpr int kProjectGroups = 1024;
 inline int project_groups(int64_t n) { int g = row_groups(n); return g < kProjectGroups ? g : kProjectGroups; }
 
-// Kernel template id of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l)
-// and CB_FRSZ2_B64_BITS(l)); l and the block size travel in BasisView.
+// Kernel template ids of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l)
+// and CB_FRSZ2_B64_BITS(l)); l and the block size travel in BasisView.  GENW
+// (l >= kWideBits) reads a lane's words as aligned 16-byte pieces, GEN as
+// single words.
 constexpr int CB_FRSZ2_GEN = 15;
+constexpr int CB_FRSZ2_GENW = 14;
+constexpr int kWideBits = 26;
+template <int FMT> constexpr bool is_generic = FMT == CB_FRSZ2_GEN || FMT == CB_FRSZ2_GENW;
 inline bool generic_b64(int f) { return f >= CB_FRSZ2_B64_BITS(3) && f <= CB_FRSZ2_B64_BITS(32); }
 inline bool generic_format(int f) {
     return (f >= CB_FRSZ2_BITS(3) && f <= CB_FRSZ2_BITS(32)) || generic_b64(f);
@@ -66,7 +71,9 @@ inline int frsz2_bits_of(int f) {
 // log2 of the FRSZ2 block size (5 for float formats: rows are padded to 32)
 inline int block_log_of(int f) { return f == CB_FRSZ2_16_B64 || f == CB_FRSZ2_32_B64 || generic_b64(f) ? 6 : 5; }
 // the template instance that runs format f
-inline int kernel_format(int f) { return generic_format(f) ? CB_FRSZ2_GEN : f; }
+inline int kernel_format(int f) {
+    return generic_format(f) ? (frsz2_bits_of(f) >= kWideBits ? CB_FRSZ2_GENW : CB_FRSZ2_GEN) : f;
+}
 // rows a basis column of format f stores: n rounded up to its block size
 inline int64_t padded_rows_of(int f, int64_t n) {
     const int64_t bs = int64_t(1) << block_log_of(f);

@@ -363,11 +363,12 @@ struct Tile<CB_FRSZ2_21> {
 // owns rows 8t .. 8t+7, i.e. codes 8s .. 8s+7 (s = t mod P, P = 4 or 8 lanes
 // per block) of block t / P, which start at bit 8 s l of the block's words:
 // word 8 s l / 32, bit 8 s l % 32 of it.  The lane loads the (at most 9) words
-// that hold its 8 codes and walks them with a two-word window that advances
-// by one word whenever the bit position passes 32; the window shifts use
-// fixed register indices, so nothing spills.
-template <>
-struct Tile<CB_FRSZ2_GEN> {
+// that hold its 8 codes -- as words, or for wide codes as up to three aligned
+// 16-byte pieces -- and walks them with a two-word window that advances by one word whenever the bit
+// position passes 32; the window shifts use fixed register indices, so
+// nothing spills.
+template <bool WIDE>
+struct GenTile {
     uint32_t y[9];
     uint32_t e;
     uint32_t off;  // bit of the lane's first code in y[0]
@@ -383,9 +384,38 @@ struct Tile<CB_FRSZ2_GEN> {
         off = start & 31u;
         // the codes end at bit start + 8 l - 1 <= 2^lb l - 1: inside the block
         const int nw = (int)((off + 8u * (uint32_t)L + 31u) >> 5);
-        const uint32_t* p = base + (int64_t)(r >> lb) * (L << (lb - 5)) + (start >> 5);
+        const int64_t w0 = (int64_t)(r >> lb) * (L << (lb - 5)) + (start >> 5);  // first word in the column
+        // Up to three 16-byte loads from the aligned word at or below w0, when
+        // the last of them ends inside the column's data (np l / 32 words);
+        // otherwise (the column's last lanes) word loads.
+        const int sh = (int)(w0 & 3);
+        const int nq = (sh + nw + 3) >> 2;
+        const bool wide = WIDE && (w0 - sh) + 4 * nq <= (((int64_t)V.np * L) >> 5);
+        if (WIDE && live && wide) {
+            const uint4* q = reinterpret_cast<const uint4*>(base + (w0 - sh));
+            uint32_t z[12];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) y[k] = (live && k < nw) ? ld4<(LM & kStream) != 0>(p + k) : 0u;
+            for (int k = 0; k < 3; ++k) {
+                const uint4 a = k < nq ? ld16<(LM & kStream) != 0>(q + k) : make_uint4(0, 0, 0, 0);
+                z[4 * k] = a.x;
+                z[4 * k + 1] = a.y;
+                z[4 * k + 2] = a.z;
+                z[4 * k + 3] = a.w;
+            }
+            // drop the sh words below w0: shifts by 2 and 1 with fixed indices,
+            // written as masks so that they stay register moves
+            const uint32_t m2 = (sh & 2) ? 0xFFFFFFFFu : 0u, m1 = (sh & 1) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) z[i] = (z[i] & ~m2) | (z[i + 2] & m2);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) z[i] = (z[i] & ~m1) | (z[i + 1] & m1);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) y[k] = z[k];
+        } else {
+            const uint32_t* p = base + w0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) y[k] = (live && k < nw) ? ld4<(LM & kStream) != 0>(p + k) : 0u;
+        }
         e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> lb)] : 0u;
     }
     __device__ __forceinline__ void codes(uint32_t* c) const {
@@ -433,6 +463,8 @@ struct Tile<CB_FRSZ2_GEN> {
         for (int q = 0; q < 8; ++q) out[q] = ldexp(m_of(c[q]), se);
     }
 };
+template <> struct Tile<CB_FRSZ2_GEN> : GenTile<false> {};
+template <> struct Tile<CB_FRSZ2_GENW> : GenTile<true> {};
 
 // Load U columns of a tile (load mode M).
 template <int FMT, int U, int LM>

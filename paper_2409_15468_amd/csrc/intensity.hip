@@ -70,6 +70,7 @@ int cb_intensity_run(const cb_basis* V, int32_t col, int32_t ops, double a, doub
     case CB_FRSZ2_16: k_intensity<CB_FRSZ2_16><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_21: k_intensity<CB_FRSZ2_21><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_GEN: k_intensity<CB_FRSZ2_GEN><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
+    case CB_FRSZ2_GENW: k_intensity<CB_FRSZ2_GENW><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_16_B64: k_intensity<CB_FRSZ2_16_B64><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     case CB_FRSZ2_32_B64: k_intensity<CB_FRSZ2_32_B64><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;
     default: k_intensity<CB_FRSZ2_32><<<G, kThreads, 0, s>>>(bv, col, ops, a, b, partials); break;

@@ -264,6 +264,7 @@ void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, con
         CB_SS_CASE(CB_FRSZ2_16)
         CB_SS_CASE(CB_FRSZ2_21)
         CB_SS_CASE(CB_FRSZ2_GEN)
+        CB_SS_CASE(CB_FRSZ2_GENW)
         CB_SS_CASE(CB_FRSZ2_16_B64)
         CB_SS_CASE(CB_FRSZ2_32_B64)
         default:

@@ -77,7 +77,7 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
     } else {
         // 8 values per lane; the 4 lanes 4u..4u+3 hold one block of 32 (the
         // 8 lanes 8u..8u+7 one block of 64)
-        const int lb = FMT == CB_FRSZ2_GEN ? bs_log : FMT == CB_FRSZ2_16_B64 ? 6 : 5;
+        const int lb = is_generic<FMT> ? bs_log : FMT == CB_FRSZ2_16_B64 ? 6 : 5;
         const int r = tile0 + 8 * lane;
         uint32_t E = 0;
 #pragma unroll
@@ -86,7 +86,7 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
         if (lb == 6) E = max(E, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)E, 0x141, 0xF, 0xF, false));
         const bool first = (lane & ((1 << (lb - 3)) - 1)) == 0;  // the block's first lane
         bad = E == 0x7FFu;
-        if constexpr (FMT == CB_FRSZ2_GEN) {
+        if constexpr (is_generic<FMT>) {
             // The lane's 8 codes go to bits 8 s l .. 8 s l + 8 l - 1 of its
             // block (s = lane % 4), streamed word by word through a 64-bit
             // accumulator.  A word the lane shares with the previous lane of
