@@ -181,8 +181,9 @@ __device__ double wg_update(const BasisView& V, int jc, const double* coef, doub
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        if (tile0 + kTile <= V.np) subtract_tile<FMT, 4, kFull>(V, jc, coef, tile0, lane, acc);
-        else subtract_tile<FMT, 4, 0>(V, jc, coef, tile0, lane, acc);
+        // single-buffered: the one-workgroup solver has no registers to spare
+        if (tile0 + kTile <= V.np) subtract_tile<FMT, 4, kFull, false>(V, jc, coef, tile0, lane, acc);
+        else subtract_tile<FMT, 4, 0, false>(V, jc, coef, tile0, lane, acc);
         double wv[8];
         load_rows<FMT>(w, tile0, lane, V.n, wv);
 #pragma unroll

@@ -214,18 +214,44 @@ __device__ __forceinline__ void project_tile_narrow(const BasisView& V, int c0, 
     }
 }
 
-template <int FMT, int U, int LM>
+// PIPE: double-buffer the next U columns' loads behind this U's multiply-adds
+// (same sums in the same order).  Off for float64, whose tiles are the widest
+// (measured no faster), and for callers short of registers.
+template <int FMT, int U, int LM, bool PIPE = FMT != CB_F64>
 __device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const double* __restrict__ h,
                                               int tile0, int lane, double* acc) {
-    for (int c = 0; c < j; c += U) {
-        Tile<FMT> t[U];
+    if constexpr (!PIPE) {
+        for (int c = 0; c < j; c += U) {
+            Tile<FMT> t[U];
+            int cols[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
+            load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
+        }
+    } else {
+        Tile<FMT> t[U], nx[U];
         int cols[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
+        for (int u = 0; u < U; ++u) cols[u] = min(u, j - 1);
         load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
+        for (int c = 0; c < j; c += U) {
+            const bool more = c + U < j;
+            if (more) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
+                for (int u = 0; u < U; ++u) cols[u] = min(c + U + u, j - 1);
+                load_tiles<FMT, U, LM>(nx, V, cols, tile0, lane);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) t[u] = nx[u];
+            }
+        }
     }
 }
 
