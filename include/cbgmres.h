@@ -22,7 +22,9 @@
  *  - Return value: a cb_status.  Nothing is thrown across the ABI.  On an
  *    error no kernel has been enqueued and cb_last_error() (thread-local)
  *    describes the cause.
- *  - Sizes n are row counts (1 <= n < 2^31 - 32); indices are 32-bit.
+ *  - Sizes n are row counts, 1 <= n <= 2^31 - 4096 (so that every 32-bit
+ *    row index a kernel forms, including its padding to 2048-row groups,
+ *    stays below 2^31); indices are 32-bit.
  *  - Alignment: basis values / FRSZ2 words and the FP64 vectors the basis
  *    kernels read or write (w, x, v_out, a solve's x) are accessed in 16-byte
  *    pieces and must be 16-byte aligned; other arrays need their element's

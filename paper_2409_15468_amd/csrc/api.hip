@@ -64,7 +64,7 @@ static double* partials_of(void* work) {
     return reinterpret_cast<double*>(static_cast<unsigned char*>(work) + kCounterBytes);
 }
 
-static bool bad_n(int64_t n) { return n < 1 || n > (int64_t)INT32_MAX - 64; }
+static bool bad_n(int64_t n) { return n < 1 || n > kMaxRows; }
 
 static int check_basis(const cb_basis* V, int need_cols) {
     if (!V) return fail(CB_ERR_INVALID_ARG, "basis descriptor is NULL");

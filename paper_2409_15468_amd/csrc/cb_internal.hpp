@@ -33,6 +33,9 @@ constexpr int kThreads = 256;     // threads per workgroup in the row kernels
 constexpr int kRowsPerWG = kThreads * kSeg;  // 2048 rows = 64 FRSZ2 blocks
 constexpr int kCounterBytes = 8192;  // ticket counters of the last-workgroup reductions
 constexpr int kMaxRestart = 512;  // largest restart length m
+// Largest row count: row indices, row-group starts and the 8-row groups past
+// them (up to 2048 * row_groups(n)) all stay below 2^31 in 32-bit arithmetic.
+constexpr int64_t kMaxRows = (int64_t(1) << 31) - 4096;
 // one-workgroup batched solver (batch.hip)
 constexpr int kBatchThreads = 512;
 constexpr int kBatchMaxN = 65536;

@@ -50,13 +50,13 @@ using namespace cb;
 extern "C" {
 
 int32_t cb_intensity_groups(int64_t n) {
-    if (n < 1) return -1;
+    if (n < 1 || n > kMaxRows) return -1;
     return project_groups(n);
 }
 
 int cb_intensity_run(const cb_basis* V, int32_t col, int32_t ops, double a, double b, double* partials,
                      void* stream) {
-    if (!V || !V->values || !partials || !valid_format(V->format) || V->n < 1 || col < 0 || col >= V->ncols ||
+    if (!V || !V->values || !partials || !valid_format(V->format) || V->n < 1 || V->n > kMaxRows || col < 0 || col >= V->ncols ||
         ops < 0 || (frsz2_bits_of(V->format) && !V->exps) || !aligned(V->values, 16) || !aligned(V->exps, 4) ||
         !aligned(partials, 8))
         return fail(CB_ERR_INVALID_ARG, "bad intensity-sweep arguments");

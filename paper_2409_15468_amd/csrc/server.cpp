@@ -275,7 +275,7 @@ using namespace cb;
 extern "C" {
 
 int64_t cb_server_request_bytes(int32_t n, int32_t nnz, int32_t m, int format) {
-    if (n < 1 || nnz < 0 || m < 1 || !valid_format(format)) return -1;
+    if (n < 1 || n > kMaxRows || nnz < 0 || m < 1 || !valid_format(format)) return -1;
     return request_bytes(n, nnz, m, format);
 }
 
@@ -303,7 +303,7 @@ int cb_server_submit(cb_server* S, int32_t n, int32_t nnz, const int32_t* row_pt
                      const double* x0_host, int32_t m, double tol, int format, uint64_t* ticket) {
     if (!S || !row_ptr_host || !b_host || !ticket || (nnz > 0 && (!col_host || !val_host)))
         return fail(CB_ERR_INVALID_ARG, "NULL argument");
-    if (n < 1 || nnz < 0 || m < 1 || m > kMaxRestart || !(tol > 0) || !valid_format(format))
+    if (n < 1 || n > kMaxRows || nnz < 0 || m < 1 || m > kMaxRestart || !(tol > 0) || !valid_format(format))
         return fail(CB_ERR_INVALID_ARG, "bad request shape");
     const int64_t bytes = request_bytes(n, nnz, m, format);
     if (bytes > (int64_t)S->budget)

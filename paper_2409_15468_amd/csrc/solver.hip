@@ -429,7 +429,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
 static int check_solve_args(const cb_csr* A, const double* b, const double* x, int32_t m,
                             double tol, int format) {
     if (!A || !b || !x) return fail(CB_ERR_INVALID_ARG, "NULL argument");
-    if (A->n < 1 || A->n > INT32_MAX - 64 || A->nnz < 0 || !A->row_ptr || (A->nnz && (!A->col || !A->val)))
+    if (A->n < 1 || A->n > kMaxRows || A->nnz < 0 || !A->row_ptr || (A->nnz && (!A->col || !A->val)))
         return fail(CB_ERR_INVALID_ARG, "bad matrix");
     if (m < 1 || m > kMaxRestart)
         return fail(CB_ERR_INVALID_ARG, "restart m=%d out of range [1, %d]", m, kMaxRestart);
@@ -446,7 +446,7 @@ using namespace cb;
 extern "C" {
 
 int64_t cbgmres_workspace_bytes(int32_t n, int32_t m, int format) {
-    if (n < 1 || m < 1 || !valid_format(format)) return -1;
+    if (n < 1 || n > kMaxRows || m < 1 || !valid_format(format)) return -1;
     return layout_of(n, m, format).total;
 }
 
@@ -478,7 +478,7 @@ int cbgmres_solve(const cb_csr* A, const double* b, double* x, int32_t m, double
 }
 
 int cb_jacobi_setup(const cb_csr* A, double* diag_inv, void* stream) {
-    if (!A || !diag_inv || A->n < 1 || !A->row_ptr || A->nnz < 0 || (A->nnz && (!A->col || !A->val)))
+    if (!A || !diag_inv || A->n < 1 || A->n > kMaxRows || !A->row_ptr || A->nnz < 0 || (A->nnz && (!A->col || !A->val)))
         return fail(CB_ERR_INVALID_ARG, "bad matrix or output");
     k_jacobi<<<(A->n + 255) / 256, 256, 0, (hipStream_t)stream>>>(A->row_ptr, A->col, A->val, A->n, diag_inv);
     CB_HIP(hipGetLastError());
@@ -486,7 +486,7 @@ int cb_jacobi_setup(const cb_csr* A, double* diag_inv, void* stream) {
 }
 
 int64_t cbgmres_precond_workspace_bytes(int32_t n, int32_t nnz, int32_t m, int format) {
-    if (n < 1 || nnz < 0 || m < 1 || !valid_format(format)) return -1;
+    if (n < 1 || n > kMaxRows || nnz < 0 || m < 1 || !valid_format(format)) return -1;
     return layout_of(n, m, format).total + al((int64_t)nnz * 8);
 }
 
@@ -630,7 +630,7 @@ static int64_t auto_solver_bytes(int32_t n, int32_t m, int32_t p, const int32_t*
 
 int64_t cbgmres_auto_workspace_bytes(int32_t n, int32_t m, int32_t probe_steps,
                                      const int32_t* candidates_host, int32_t count) {
-    if (n < 1 || m < 1 || m > kMaxRestart || probe_steps < 1 || probe_steps > kMaxRestart ||
+    if (n < 1 || n > kMaxRows || m < 1 || m > kMaxRestart || probe_steps < 1 || probe_steps > kMaxRestart ||
         !candidates_host || count < 1 || count > CB_AUTO_MAX_CANDIDATES)
         return -1;
     for (int32_t i = 0; i < count; ++i)

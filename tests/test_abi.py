@@ -202,3 +202,24 @@ def test_misaligned_pointers_rejected_without_device_work():
                            None) == cb.CB_ERR_INVALID_ARG
     assert L.cbgmres_solve(C.byref(A), 260, 256, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res),
                            None) == cb.CB_ERR_INVALID_ARG
+
+
+def test_row_count_limit_without_device_work():
+    """n may not exceed 2^31 - 4096: every 32-bit row index a kernel forms,
+    padding to 2048-row groups included, stays below 2^31.  Pointers here are
+    never dereferenced."""
+    L = cb.lib()
+    nmax = (1 << 31) - 4096
+    assert cb.cb_basis_column_bytes("frsz2_32", nmax) > 0
+    assert cb.cbgmres_workspace_bytes(nmax, 10, "float64") > 0
+    assert cb.cbgmres_workspace_bytes(nmax + 1, 10, "float64") == -1
+    assert cb.cb_reduce_workspace_bytes(nmax + 1, 4) == -1
+    assert cb.cb_intensity_groups(nmax + 1) == -1
+    V = cb.cb_basis(5, nmax + 1, 4, 0, 256, 256)
+    assert L.cb_basis_load(C.byref(V), 0, 256, None) == cb.CB_ERR_INVALID_ARG
+    assert L.frsz2_compress(256, nmax + 1, 21, 256, 256, None, None) == cb.CB_ERR_INVALID_ARG
+    A = cb.cb_csr(nmax + 1, 5000, 256, 256, 256)
+    res = cb.cb_result()
+    assert L.cbgmres_solve(C.byref(A), 256, 256, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res),
+                           None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_jacobi_setup(C.byref(A), 256, None) == cb.CB_ERR_INVALID_ARG
