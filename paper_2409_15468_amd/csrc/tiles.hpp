@@ -167,24 +167,29 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
     return bad;
 }
 
-// One wave's columns [c0, c1) of its tile, 8 at a time; the wave's sums for
-// column c are added to red[c - c0].  The loads of the next 8 columns are issued
-// before the current 8 are reduced across the wave.
+// One wave's columns [c0, c1) of its tile, 8 at a time, the last 8 first; the
+// wave's sums for column c are added to red[c - c0].  The loads of the next 8
+// columns are issued before the current 8 are reduced across the wave.  The
+// passes of a step alternate direction -- projections run down the columns,
+// updates up -- so that each pass starts on the columns the previous pass read
+// last, which the caches still hold.  Each column's sum does not depend on the
+// order in which columns are visited.
 template <int FMT, int LM>
 __device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1, int tile0, int lane,
                                              const double* wv, double* red) {
+    const int last = c0 + ((c1 - c0 - 1) / 8) * 8;  // first column of the last group of 8
     Tile<FMT> t[8];
     int cols[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) cols[u] = min(c0 + u, c1 - 1);
+    for (int u = 0; u < 8; ++u) cols[u] = min(last + u, c1 - 1);
     load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
-    for (int c = c0; c < c1; c += 8) {
+    for (int c = last; c >= c0; c -= 8) {
         double p[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) p[u] = t[u].dot(wv);
-        if (c + 8 < c1) {
+        if (c - 8 >= c0) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) cols[u] = min(c + 8 + u, c1 - 1);
+            for (int u = 0; u < 8; ++u) cols[u] = c - 8 + u;
             load_tiles<FMT, 8, LM>(t, V, cols, tile0, lane);
         }
         const double sum = wave_sum8(p);  // lane 8u holds column c + u
@@ -197,7 +202,7 @@ __device__ __forceinline__ void project_tile(const BasisView& V, int c0, int c1,
 template <int FMT, int LM>
 __device__ __forceinline__ void project_tile_narrow(const BasisView& V, int c0, int c1, int tile0, int lane,
                                                     const double* wv, double* red) {
-    for (int c = c0; c < c1; c += 8) {
+    for (int c = c0 + ((c1 - c0 - 1) / 8) * 8; c >= c0; c -= 8) {
         double p[8];
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
