@@ -470,7 +470,7 @@ def main():
                          "0: the runtime default); streams beyond the queue count share queues")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU; multi-GPU runs are not supported (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "serving" and args.serve_hw_queues:
