@@ -87,3 +87,32 @@ def test_budget_forces_queueing_and_rejects_oversize():
         srv.submit(big.A.row_ptr, big.A.col, big.A.val, big.b, 100, 1e-8, "float64")
     assert ei.value.status == cb.CB_ERR_OVER_BUDGET
     srv.close()
+
+
+def test_generic_and_block64_formats_are_served_by_the_solve_lanes():
+    """Small requests in the generic-width and block-64 FRSZ2 formats (which
+    the one-workgroup batched solver does not run) are admitted and solved by
+    the solve lanes, with the same result as a direct cbgmres_solve."""
+    s = synth.plain_2d(N=40, seed=9)
+    fmts = ["frsz2_12", "frsz2b64_32", "frsz2b64_21", "frsz2_32"]
+    srv = cb.Server(4 << 30, 0, lanes=2)
+
+    class R:
+        def __init__(self, rid, fmt):
+            self.rid, self.m, self.tol, self.fmt = rid, 30, 1e-10, fmt
+    items = [(R(i, f), s) for i, f in enumerate(fmts)]
+    out = run_all(srv, items)
+    srv.close()
+    A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    b = torch.from_numpy(s.b).cuda()
+    for r, _ in items:
+        x, res, _ = out[r.rid]
+        assert res["status"] == 0 and res["converged"], (r.fmt, res)
+        xd = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+        ref, _ = cb.cbgmres_solve(A, b, xd, 30, 1e-10, r.fmt)
+        torch.cuda.synchronize()
+        if r.fmt == "frsz2_32":  # batched: another kernel, its own reduction order
+            assert abs(res["iterations"] - ref["iterations"]) <= max(1, int(np.ceil(0.02 * ref["iterations"])))
+        else:  # the solve lanes run cbgmres_solve itself: bit for bit
+            assert res["iterations"] == ref["iterations"], r.fmt
+            assert np.array_equal(x.view(np.uint64), xd.cpu().numpy().view(np.uint64)), r.fmt
