@@ -191,13 +191,10 @@ __global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int 
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
         const bool full = tile0 + kTile <= V.np;
-        if (stream) {
-            if (full) subtract_tile<FMT, U, kFull | kStream>(V, j, hc, tile0, lane, acc);
-            else subtract_tile<FMT, U, kStream>(V, j, hc, tile0, lane, acc);
-        } else {
-            if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
-            else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
-        }
+        // ordinary (cache-allocating) loads even for a streaming basis: the
+        // projection below re-reads these columns, last first, right away
+        if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
+        else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
         double wv[8];
         load_rows<FMT>(w, tile0, lane, V.n, wv);
         double t = 0.0;
