@@ -221,8 +221,9 @@ __device__ __forceinline__ void project_tile_narrow(const BasisView& V, int c0, 
 
 // PIPE: double-buffer the next U columns' loads behind this U's multiply-adds
 // (same sums in the same order).  Off for float64, whose tiles are the widest
-// (measured no faster), and for callers short of registers.
-template <int FMT, int U, int LM, bool PIPE = FMT != CB_F64>
+// (measured no faster), for the generic widths, whose tiles hold up to nine
+// words (measured 20-30% slower with it), and for callers short of registers.
+template <int FMT, int U, int LM, bool PIPE = FMT != CB_F64 && !is_generic<FMT>>
 __device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const double* __restrict__ h,
                                               int tile0, int lane, double* acc) {
     if constexpr (!PIPE) {
