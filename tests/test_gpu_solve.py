@@ -145,6 +145,25 @@ def test_iterative_refinement_precision_form():
     assert np.linalg.norm(x - ref64.x) / np.linalg.norm(ref64.x) < 1e-10
 
 
+@pytest.mark.parametrize("fmt,inner_tol", [("frsz2_21", 1e-6), ("float16", 1e-3), ("frsz2b64_32", 1e-8)])
+def test_iterative_refinement_other_inner_formats(fmt, inner_tol):
+    """The refinement with other inner bases and inner tolerances: the same
+    outer steps as the oracle, inner steps within 2%, FP64 accuracy."""
+    s = synth.banded_random(n=12000, half_band=500, seed=5)
+    Ad = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+    bd = torch.from_numpy(s.b).cuda()
+    xd = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    res = cb.cbgmres_ir_solve(Ad, bd, xd, 60, inner_tol, 1e-12, fmt)
+    x = xd.cpu().numpy()
+    ref = oracle.ir_solve(s.A, s.b, 60, inner_tol, 1e-12, fmt)
+    print(fmt, res["restarts"], res["iterations"], "| oracle", ref.outer, ref.iterations)
+    assert res["converged"] and ref.converged
+    assert host_rrn(s.A, s.b, x) <= 1e-12 * (1 + 1e-6)
+    assert res["restarts"] == ref.outer
+    assert within_2pct(res["iterations"], ref.iterations)
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) < 1e-10
+
+
 def test_tall_system_short_restart():
     """n = 5e6 with GMRES(1): the norm of b uses one partial per 2048-row group
     (2442 of them), more than the projection partials of a restart length of
