@@ -223,3 +223,16 @@ def test_row_count_limit_without_device_work():
     assert L.cbgmres_solve(C.byref(A), 256, 256, 10, 1e-8, 5, None, None, 0, None, 0, C.byref(res),
                            None) == cb.CB_ERR_INVALID_ARG
     assert L.cb_jacobi_setup(C.byref(A), 256, None) == cb.CB_ERR_INVALID_ARG
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/cbgmres.h compiles as C99 (no C++ or HIP types in the ABI)."""
+    src = tmp_path / "use.c"
+    src.write_text('#include "cbgmres.h"\n'
+                   'int f(cb_csr* A, const double* b, double* x, void* s) {\n'
+                   '    cb_result r;\n'
+                   '    return cbgmres_solve(A, b, x, 30, 1e-8, CB_FRSZ2_BITS(12), 0, 0, 0, 0, 0, &r, s);\n'
+                   '}\n')
+    out = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
+                          "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
