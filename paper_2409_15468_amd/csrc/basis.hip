@@ -304,7 +304,7 @@ void launch_load(int fmt, const cb_basis& V, int col, double* x, hipStream_t s) 
 void launch_project(int fmt, const cb_basis& V, int j, const double* w, double* partials,
                     const int* guard, const Epi& e, hipStream_t s) {
     BasisView b = view_of(V);
-    const int G = project_groups(V.n);
+    const int G = dot_groups(V.n);
     // Column chunks (multiples of 8 columns) only while the launch has fewer
     // waves than the GPU keeps resident (~2048 at this kernel's register
     // use): every workgroup pays a fixed tail (its partial stores and ticket),

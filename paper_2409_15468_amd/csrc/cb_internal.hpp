@@ -49,6 +49,10 @@ __host__ __device__ inline int row_groups_dev(int np) { return (np + kRowsPerWG 
 // workgroups of the basis kernels: one per row group, at most kProjectGroups
 constexpr int kProjectGroups = 1024;
 inline int project_groups(int64_t n) { int g = row_groups(n); return g < kProjectGroups ? g : kProjectGroups; }
+// The projection alone (h = V^T w) runs best with half as many, longer
+// workgroups: measured 2% faster at 2^24 rows, where the updates are not.
+constexpr int kDotGroups = 512;
+inline int dot_groups(int64_t n) { int g = project_groups(n); return g < kDotGroups ? g : kDotGroups; }
 
 // Kernel template ids of the generic-l FRSZ2 codec (formats CB_FRSZ2_BITS(l)
 // and CB_FRSZ2_B64_BITS(l)); l and the block size travel in BasisView.  GENW
