@@ -72,7 +72,7 @@ def lib():
             "or_cgs_subtract": (None, [i64, i32, P, i64, P, P]),
             "or_gmres": (i32, [i64, P, P, P, P, P, i32, d, i32, P, P, P, i64]),
             "or_gmres_cycle": (None, [i64, P, P, P, P, d, i32, i32, d, i32, d, i32, P, P, P, P,
-                                      P, P, P, P]),
+                                      P, P, P, P, P]),
             "or_ir_solve": (i32, [i64, P, P, P, P, P, i32, d, d, i32, i32, P]),
             "or_gmres_pc": (i32, [i64, P, P, P, P, P, P, i32, d, i32, P, P, P, i64]),
             "or_jacobi_diag_inv": (None, [i64, P, P, P, P]),
@@ -262,6 +262,7 @@ class Cycle:
     Vdec: np.ndarray     # float64 n x (m+1), Fortran order: D(Q(v_i))
     R: np.ndarray        # (m+1) x m rotated Hessenberg (upper triangle valid)
     Hraw: np.ndarray     # (m+1) x m unrotated Hessenberg
+    Vfp: np.ndarray      # float64 n x (m+1), Fortran order: the FP64 v_i (SpMV input, Q's input)
     y: np.ndarray        # least-squares solution, length steps
     gabs_hist: np.ndarray
 
@@ -279,14 +280,15 @@ def gmres_cycle(A, r, beta: float, m: int, fmt="float64", eta: float = 0.7071067
     Vdec = np.zeros((n, m + 1), np.float64, order="F")
     R = np.zeros((m + 1, m), np.float64, order="F")
     Hraw = np.zeros((m + 1, m), np.float64, order="F")
+    Vfp = np.zeros((n, m + 1), np.float64, order="F")
     y = np.zeros(m, np.float64)
     hist = np.zeros(m, np.float64)
     ci = _CycleInfo()
     lib().or_gmres_cycle(n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(r), beta, m, f, eta,
                          int(literal_breakdown), tol_abs, max_steps, _p(enc), _p(exps),
-                         _p(Vdec), _p(R), _p(Hraw), _p(y), _p(hist), C.byref(ci))
+                         _p(Vdec), _p(R), _p(Hraw), _p(Vfp), _p(y), _p(hist), C.byref(ci))
     return Cycle(ci.steps, ci.reorths, bool(ci.breakdown), ci.status, ci.gabs, enc, exps,
-                 Vdec, R, Hraw, y[:ci.steps].copy(), hist[:ci.steps].copy())
+                 Vdec, R, Hraw, Vfp, y[:ci.steps].copy(), hist[:ci.steps].copy())
 
 
 @dataclass

@@ -407,6 +407,8 @@ typedef struct {
  *   H         (m+1)*m doubles, column-major, ld m+1: on return the rotated
  *             upper-triangular R in rows 0..m'-1
  *   Hraw      nullable; the unrotated Hessenberg matrix, same layout
+ *   Vfp       nullable; n*(m+1) doubles: the FP64 vectors v_i themselves
+ *             (column stride n), i.e. what the SpMV reads and what Q encodes
  *   y         m doubles: the least-squares solution of R y = g
  *   hist      nullable; |g_{j+1}| per step
  * Stops after m steps, when |g_{j+1}| <= tol_abs, on breakdown, or after
@@ -414,7 +416,7 @@ typedef struct {
 static void gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                         const double* dinv, const double* r, double beta, int m, int fmt, double eta,
                         int literal, double tol_abs, int max_steps, unsigned char* enc, uint32_t* exps,
-                        double* Vdec, double* H, double* Hraw, double* y, double* hist,
+                        double* Vdec, double* H, double* Hraw, double* Vfp, double* y, double* hist,
                         or_cycle_info* info) {
     int64_t cb = or_basis_col_bytes(fmt, n);
     int64_t nbk = nblocks_of(n);
@@ -430,6 +432,7 @@ static void gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, c
     if (Hraw) memset(Hraw, 0, (size_t)(m + 1) * m * 8);
     /* Step 1: v = r / beta (IEEE division per entry), V_1 = [Q(v)] */
     for (int64_t k = 0; k < n; ++k) v[k] = r[k] / beta;
+    if (Vfp) memcpy(Vfp, v, (size_t)n * 8);
     if (or_basis_encode(fmt, v, n, enc, exps)) { info->status = 2; goto done; }
     or_basis_decode(fmt, enc, exps, n, Vdec);
     for (int i = 0; i <= m; ++i) g[i] = 0.0;
@@ -483,6 +486,7 @@ static void gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, c
         }
         /* Steps 13-14: normalise (IEEE division) and store the new vector */
         for (int64_t k = 0; k < n; ++k) v[k] = w[k] / hn;
+        if (Vfp) memcpy(Vfp + (int64_t)(j + 1) * n, v, (size_t)n * 8);
         if (or_basis_encode(fmt, v, n, enc + (j + 1) * cb, exps + (j + 1) * nbk)) {
             info->status = 2;
             goto done;
@@ -502,10 +506,10 @@ done:
 void or_gmres_cycle(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* val,
                     const double* r, double beta, int m, int fmt, double eta, int literal,
                     double tol_abs, int max_steps, unsigned char* enc, uint32_t* exps,
-                    double* Vdec, double* H, double* Hraw, double* y, double* hist,
+                    double* Vdec, double* H, double* Hraw, double* Vfp, double* y, double* hist,
                     or_cycle_info* info) {
     gmres_cycle(n, row_ptr, col, val, NULL, r, beta, m, fmt, eta, literal, tol_abs, max_steps, enc,
-                exps, Vdec, H, Hraw, y, hist, info);
+                exps, Vdec, H, Hraw, Vfp, y, hist, info);
 }
 
 /* Jacobi preconditioner M = diag(A) (Fig. 1's M, the simplest choice):
@@ -564,7 +568,7 @@ int or_gmres_pc(int64_t n, const int32_t* row_ptr, const int32_t* col, const dou
         st->restarts += 1;
         or_cycle_info ci;
         gmres_cycle(n, row_ptr, col, val, dinv, r, beta, m, fmt, eta, literal, tol * nb,
-                    max_iters - st->iterations, enc, exps, Vdec, H, NULL, y, ch, &ci);
+                    max_iters - st->iterations, enc, exps, Vdec, H, NULL, NULL, y, ch, &ci);
         for (int j = 0; j < ci.steps; ++j) {
             if (hist && st->iterations + j < hist_cap) hist[st->iterations + j] = ch[j] / nb;
         }
