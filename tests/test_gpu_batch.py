@@ -10,6 +10,7 @@ import pytest
 import oracle
 import paper_2409_15468_amd as cb
 import synth
+from tests._golden import count_agrees, inputs_digest
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -88,16 +89,10 @@ def test_plain_config_all_formats_one_batch():
               f"oracle iters={ref.iterations}; err vs fp64 oracle={err:.2e}")
         assert r["status"] == 0 and r["converged"]
         assert host_rrn(s.A, s.b, x) <= 1e-10 * (1 + 1e-6)
-        if fmt == "float16" and not within_2pct(r["iterations"], ref.iterations):
-            # see the multi-workgroup solver's test: an 11-bit basis amplifies
-            # last-bit differences; the count must lie in the oracle's own spread
-            rng = np.random.default_rng(0)
-            spread = [oracle.gmres(s.A, s.b * (1 + 2.0 ** -52 * rng.choice([-1.0, 0.0, 1.0], s.A.n)),
-                                   50, 1e-10, fmt).iterations for _ in range(6)]
-            assert 0.98 * min(spread + [ref.iterations]) <= r["iterations"] <= \
-                1.02 * max(spread + [ref.iterations])
-        else:
-            assert within_2pct(r["iterations"], ref.iterations), (fmt, r["iterations"], ref.iterations)
+        # see the multi-workgroup solver's test: an 11- or 15-bit basis may
+        # land in the oracle's stored spread under last-bit perturbations of b
+        assert count_agrees(r["iterations"], ref.iterations, "plain64_m50", fmt, inputs_digest(s.A, s.b)), \
+            (fmt, r["iterations"], ref.iterations)
         assert err < 1e-6
 
 

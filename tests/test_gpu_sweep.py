@@ -5,6 +5,7 @@ stated relative residual (recomputed on the host), take within 2% of the
 oracle's iteration count (tests/golden/sweep_oracle_<format>.json, written by
 make_sweep_reference.py from the oracle), and its solution is compared with
 the oracle's at the 4096 stored sample rows."""
+import hashlib
 import json
 import os
 
@@ -35,6 +36,8 @@ def test_sweep_format(system, fmt):
     s, A, b, ws = system
     with open(os.path.join(GOLDEN, f"sweep_oracle_{fmt}.json")) as f:
         ref = json.load(f)
+    # the stored results were computed from these very inputs
+    assert hashlib.sha256(s.A.sha256().encode() + s.b.tobytes()).hexdigest() == ref["inputs_sha256"]
     x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
     res, _ = cb.cbgmres_solve(A, b, x, 100, 1e-10, fmt, workspace=ws)
     torch.cuda.synchronize()
