@@ -85,6 +85,18 @@ def main():
                                              "inputs_sha256": digest(A, b, x0)}
         print("auto17", fmt, ref, sorted(pert), f"{time.time() - t0:.0f}s", flush=True)
 
+    # served requests (the first 24 of the seeded stream with n <= 40^3) that
+    # the serving test checks against the oracle: those with n <= 10^4 and a
+    # basis of at most 16 bits per value
+    for r in synth.serving_requests(count=24, seed=4, n_max=40 ** 3):
+        if r.n > 10000 or r.fmt not in ("float16", "frsz2_16"):
+            continue
+        sy = r.system()
+        ref, pert = counts(lambda bb: oracle.gmres(sy.A, bb, r.m, r.tol, r.fmt), sy.b, 6)
+        cases[f"served24_r{r.rid}/{r.fmt}"] = {"oracle": ref, "perturbed": pert,
+                                              "inputs_sha256": digest(sy.A, sy.b)}
+        print("served", r.rid, r.fmt, ref, sorted(pert), f"{time.time() - t0:.0f}s", flush=True)
+
     out = {
         "recipe": "b_k = b * (1 + 2^-52 s_k), s_k in {-1,0,1}^n from numpy default_rng(0) drawn in sequence; "
                   "'oracle' is the unperturbed count, 'perturbed' the K perturbed counts",

@@ -37,6 +37,11 @@ def _case_inputs(case):
         x0 = rng.standard_normal(A.n) * 0.1
         pr = oracle.auto_probe(A, b, x0, fmt, 9, 1e-9)
         return A, b, x0, lambda bb: oracle.gmres(A, bb, 25, 1e-9, fmt, x0=pr.x)
+    if case.startswith("served24_r"):
+        rid = int(case.split("/")[0][len("served24_r"):])
+        r = synth.serving_requests(count=24, seed=4, n_max=40 ** 3)[rid]
+        s = r.system()
+        return s.A, s.b, None, lambda bb: oracle.gmres(s.A, bb, r.m, r.tol, r.fmt)
     raise KeyError(case)
 
 
@@ -58,3 +63,19 @@ def test_sweep_golden_inputs_match_the_generator():
     for fmt in ["float64", "float32", "float16", "frsz2_16", "frsz2_21", "frsz2_32"]:
         with open(os.path.join(GOLDEN, f"sweep_oracle_{fmt}.json")) as f:
             assert json.load(f)["inputs_sha256"] == digest, fmt
+
+
+def test_microbench_golden_is_the_oracles_first_column():
+    """The first column of the stored microbenchmark reference: its inputs,
+    its frsz2_32 encoding hash and its projection are the oracle's."""
+    import hashlib
+    with open(os.path.join(GOLDEN, "microbench_oracle.json")) as f:
+        ref = json.load(f)
+    n = ref["n"]
+    w = synth.basis_probe_vector(n, ref["seed"])
+    assert hashlib.sha256(w.tobytes()).hexdigest() == ref["w_sha256"]
+    col = next(synth.basis_columns(n, 1, ref["seed"]))
+    assert hashlib.sha256(col.tobytes()).hexdigest() == ref["column_sha256"][0]
+    exps, words, _ = oracle.frsz2_encode(col, 32)
+    assert hashlib.sha256(words.tobytes() + exps.tobytes()).hexdigest() == ref["encoded_sha256"]["32"][0]
+    assert oracle.dot(oracle.frsz2_decode(exps, words, n, 32), w) == ref["h"]["32"][0]

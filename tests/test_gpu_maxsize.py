@@ -3,7 +3,10 @@ row index a kernel forms stays below 2^31): the frsz2_21 codec (codes that
 straddle words) on a full column, checked bit-exactly against the oracle on
 sampled blocks (the first, the last and 2000 seeded ones) and by the
 truncation property on every value; the fused projection and update with two
-frsz2_32 columns, checked against FP64 sums of the decoded columns."""
+frsz2_32 columns, checked against the oracle: h against the oracle's decode of
+the stored words and its compensated dot product (in 2^27-row chunks whose
+compensated sums are added by the oracle's compensated sum), the update on
+sampled rows against the oracle's random-access decode."""
 import numpy as np
 import pytest
 
@@ -69,26 +72,52 @@ def test_projection_and_update_at_the_row_limit():
         del v
     w = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
     h = cb.cb_cgs_project(V, 2, w).cpu().numpy()
-    dec = torch.empty(n, dtype=torch.float64, device="cuda")
-    ref, scale = [], []
+    torch.cuda.synchronize()
+    # the oracle's h from the stored words, chunk by chunk (chunks are whole
+    # blocks), and the scale sum |v~ w| of the parity bound
+    chunk = 1 << 27
+    part = [[], []]
+    absp = [[], []]
+    for s0 in range(0, n, chunk):
+        e0 = min(n, s0 + chunk)
+        wc = w[s0:e0].cpu().numpy()
+        for c in range(2):
+            words = V.column(c).view(torch.int32)[s0:e0].cpu().numpy().view(np.uint32)
+            ex = u32(V.column_exps(c)[s0 // 32:(e0 + 31) // 32])
+            dec = oracle.frsz2_decode(ex, words, e0 - s0, 32)
+            part[c].append(oracle.dot(dec, wc))
+            absp[c].append(oracle.dot(np.abs(dec), np.abs(wc)))
+            del words, ex, dec
+        del wc
     for c in range(2):
-        cb.cb_basis_load(V, c, dec)
-        ref.append(float(torch.dot(dec, w)))
-        scale.append(float((dec.abs() * w.abs()).sum()))
-    for c in range(2):
-        assert abs(h[c] - ref[c]) <= 1e-12 * scale[c], (c, h[c], ref[c])
-    # w -= V h on sampled rows against the decoded columns, and the fused norm
-    rows = torch.from_numpy(np.unique(np.concatenate([[0, n - 1], np.random.default_rng(4).integers(0, n, 4096)]))).cuda()
+        ones = np.ones(len(part[c]))
+        ref = oracle.dot(np.array(part[c]), ones)
+        scale = oracle.dot(np.array(absp[c]), ones)
+        print(f"column {c}: h {h[c]!r} oracle {ref!r} scale {scale:.3e}")
+        assert abs(h[c] - ref) <= 1e-12 * scale, (c, h[c], ref)
+    # w -= V h on sampled rows against the oracle's random-access decode of
+    # the blocks that hold them, and the fused norm
+    rows_np = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(4).integers(0, n, 4096)]))
+    rows = torch.from_numpy(rows_np).cuda()
     w0 = w[rows].cpu().numpy()
-    d0 = [None, None]
+    d0 = [np.empty(rows_np.size), np.empty(rows_np.size)]
     for c in range(2):
-        cb.cb_basis_load(V, c, dec)
-        d0[c] = dec[rows].cpu().numpy()
+        blk = torch.from_numpy(rows_np // 32).cuda()
+        words = V.column(c).view(torch.int32).view(-1, 32)[blk].cpu().numpy().view(np.uint32)
+        ex = u32(V.column_exps(c)[blk])
+        for k, r in enumerate(rows_np):
+            d0[c][k] = oracle.frsz2_decode_value(ex[k:k + 1], words[k], int(r % 32), 32)
     hd = torch.from_numpy(h).cuda()
     nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
     cb.cb_cgs_subtract(V, 2, hd, w, norm2=nrm)
     got = w[rows].cpu().numpy()
     want = w0 - (h[0] * d0[0] + h[1] * d0[1])
     assert np.all(np.abs(got - want) <= 1e-14 * (np.abs(w0) + np.abs(h[0] * d0[0]) + np.abs(h[1] * d0[1])))
-    ww = float(torch.dot(w, w))
+    # the norm: the oracle's compensated sum of squares over the updated w
+    sq = []
+    for s0 in range(0, n, chunk):
+        wc = w[s0:min(n, s0 + chunk)].cpu().numpy()
+        sq.append(oracle.dot(wc, wc))
+        del wc
+    ww = oracle.dot(np.array(sq), np.ones(len(sq)))
     assert abs(float(nrm.item()) - ww) <= 1e-12 * ww
