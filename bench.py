@@ -16,8 +16,9 @@ FETCH_SIZE / WRITE_SIZE counter summary under profiles/ (scaled by the same
 counters' reading for a 1 GiB copy), reported only while the kernel sources
 hash to the value recorded there; otherwise null.
 
-CPU baseline: the FP64 oracle, single thread, on the first 80 Arnoldi steps of
-the same solve, scaled to the whole solve by basis-column work.
+CPU baseline: the FP64 oracle's whole frsz2_32 solve of the same system,
+single thread, timed in a background thread beside the GPU legs; the host's
+CPU model and logical core count are reported with it.
 
 Other workloads (--workload): `serving` runs the seeded request stream through
 the continuous-batching server (p50/p99 latency, solves/s); `precision` runs
@@ -96,17 +97,19 @@ def timed_solves(cb, torch, A, b, x, fmt, m, tol, steps, warmup, ws):
 
 
 def event_time(torch, fn, reps):
-    """Average duration of fn() over reps launches, HIP events on the current
-    stream (the stream the library launches on)."""
+    """Duration of fn() from HIP events recorded around each of `reps`
+    launches on the current stream (the stream the library launches on), after
+    one untimed launch: (minimum, median) in seconds."""
     s = torch.cuda.current_stream()
     fn()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record(s)
         fn()
-    e1.record(s)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / reps
+        e1.record(s)
+    ev[-1][1].synchronize()
+    t = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
+    return t[0], t[len(t) // 2]
 
 
 def microbench(cb, torch, n, ncols, reps, formats):
@@ -126,23 +129,23 @@ def microbench(cb, torch, n, ncols, reps, formats):
         h = torch.empty(ncols, dtype=torch.float64, device="cuda")
         work = torch.empty(cb.cb_reduce_workspace_bytes(n, ncols) // 8 + 1, dtype=torch.float64,
                            device="cuda")
-        t_dot = event_time(torch, lambda: cb.cb_cgs_project(V, ncols, w, h, work), reps)
+        t_dot, m_dot = event_time(torch, lambda: cb.cb_cgs_project(V, ncols, w, h, work), reps)
         wt = w.clone()
         hs = torch.full((ncols,), 1e-3, dtype=torch.float64, device="cuda")
         n2 = torch.empty(1, dtype=torch.float64, device="cuda")
-        t_upd = event_time(torch, lambda: cb.cb_cgs_subtract(V, ncols, hs, wt, n2, work), reps)
+        t_upd, m_upd = event_time(torch, lambda: cb.cb_cgs_subtract(V, ncols, hs, wt, n2, work), reps)
         xo = torch.empty(n, dtype=torch.float64, device="cuda")
-        t_dec = event_time(torch, lambda: cb.cb_basis_load(V, 7, xo), reps * 4)
-        t_enc = event_time(torch, lambda: cb.cb_basis_store(V, 7, cols[7]), reps * 4)
+        t_dec, m_dec = event_time(torch, lambda: cb.cb_basis_load(V, 7, xo), reps * 4)
+        t_enc, m_enc = event_time(torch, lambda: cb.cb_basis_store(V, 7, cols[7]), reps * 4)
         dot_bytes = ncols * n * bv + 8 * n
         upd_bytes = ncols * n * bv + 16 * n
         codec_bytes = (8 + bv) * n
         out[fmt] = {
             "bytes_per_value": bv,
-            "dot_s": t_dot, "dot_GBs": dot_bytes / t_dot / 1e9,
-            "update_s": t_upd, "update_GBs": upd_bytes / t_upd / 1e9,
-            "decompress_GBs": codec_bytes / t_dec / 1e9,
-            "compress_GBs": codec_bytes / t_enc / 1e9,
+            "dot_s": t_dot, "dot_GBs": dot_bytes / t_dot / 1e9, "dot_median_s": m_dot,
+            "update_s": t_upd, "update_GBs": upd_bytes / t_upd / 1e9, "update_median_s": m_upd,
+            "decompress_s": t_dec, "decompress_GBs": codec_bytes / t_dec / 1e9, "decompress_median_s": m_dec,
+            "compress_s": t_enc, "compress_GBs": codec_bytes / t_enc / 1e9, "compress_median_s": m_enc,
         }
         log(f"microbench {fmt}: dot {out[fmt]['dot_GBs']:.0f} GB/s, update {out[fmt]['update_GBs']:.0f} GB/s, "
             f"decompress {out[fmt]['decompress_GBs']:.0f} GB/s, compress {out[fmt]['compress_GBs']:.0f} GB/s")
@@ -151,27 +154,49 @@ def microbench(cb, torch, n, ncols, reps, formats):
     return out
 
 
-def cpu_baseline(s, gpu_iters, gpu_cycles, m, sample_steps=80):
-    """The oracle on the first `sample_steps` Arnoldi steps of the same solve,
-    scaled to the whole solve by the Gram-Schmidt work, which dominates the
-    oracle's time: step j of a cycle costs in proportion to its j + 1 basis
-    columns."""
-    import oracle
-    t = time.perf_counter()
-    r = oracle.gmres(s.A, s.b, m, 1e-10, "frsz2_32", max_iters=sample_steps)
-    dt = time.perf_counter() - t
-    steps = [m] * (gpu_cycles - 1) + [gpu_iters - m * (gpu_cycles - 1)]
-    work = sum(sum(j + 1 for j in range(k)) for k in steps)
-    sample_work = sum(j + 1 for j in range(r.iterations))
-    return {
-        "value": dt * work / sample_work,
-        "unit": "s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"the first {r.iterations} Arnoldi steps of the same frsz2_32 solve took {dt:.2f}s on one "
-                  f"host core; scaled by basis-column work ({work} vs {sample_work} column passes) to the "
-                  f"GPU solve's {gpu_iters} steps in {gpu_cycles} cycles",
-    }
+def host_cpu():
+    """The host's CPU model (from /proc/cpuinfo) and its logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+class CpuBaseline:
+    """The oracle's whole frsz2_32 solve of the benchmark system, timed on one
+    host core in a thread of its own (the oracle is a C library called
+    through ctypes, which releases the interpreter lock, so the thread runs
+    beside the GPU legs without holding them up)."""
+
+    def __init__(self, s, m, tol):
+        import threading
+        import oracle
+        self.out = None
+
+        def run():
+            t = time.perf_counter()
+            r = oracle.gmres(s.A, s.b, m, tol, "frsz2_32")
+            self.out = (time.perf_counter() - t, r.iterations, r.restarts, bool(r.converged))
+        self.thread = threading.Thread(target=run, daemon=True)
+        self.thread.start()
+
+    def result(self, gpu_iters):
+        self.thread.join()
+        dt, iters, cycles, conv = self.out
+        model, cores = host_cpu()
+        return {
+            "value": dt, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole frsz2_32 solve of the same system by the oracle ({iters} Arnoldi steps in "
+                      f"{cycles} cycles, converged={conv}; GPU: {gpu_iters} steps), single thread, run "
+                      f"beside the GPU legs",
+            "host_cpu": model, "host_logical_cores": cores,
+        }
 
 
 def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
@@ -256,6 +281,10 @@ def precision_bench(cb, torch, steps, warmup):
     A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
     b = torch.from_numpy(s.b).cuda()
     x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+    # one caller-owned workspace for every solve: nothing is allocated in the
+    # timed region
+    ws = torch.empty(max(cb.cbgmres_ir_workspace_bytes(s.A.n, 100, "frsz2_16"),
+                         cb.cbgmres_workspace_bytes(s.A.n, 100, "float64")), dtype=torch.uint8, device="cuda")
     out = {}
 
     def run(fn):
@@ -274,15 +303,15 @@ def precision_bench(cb, torch, steps, warmup):
     # oracle pins; looser and tighter inner solves are timed beside it
     inner = {}
     for itol in (1e-2, 1e-6, 1e-8):
-        t_i, r_i = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, itol, 1e-12, "frsz2_16"))
+        t_i, r_i = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, itol, 1e-12, "frsz2_16", workspace=ws))
         inner[f"{itol:g}"] = {"seconds": t_i, "iterations": r_i["iterations"], "outer": r_i["restarts"],
                               "converged": bool(r_i["converged"])}
         log(f"precision ir inner_tol {itol:g}: {t_i * 1e3:.1f} ms, {r_i['iterations']} iterations, "
             f"{r_i['restarts']} outer")
     out["ir_inner_tol_sweep"] = inner
-    t_ir, r_ir = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, 1e-4, 1e-12, "frsz2_16"))
+    t_ir, r_ir = run(lambda: cb.cbgmres_ir_solve(A, b, x, 100, 1e-4, 1e-12, "frsz2_16", workspace=ws))
     x_ir = x.cpu().numpy()
-    t_64, r_64 = run(lambda: cb.cbgmres_solve(A, b, x, 100, 1e-12, "float64")[0])
+    t_64, r_64 = run(lambda: cb.cbgmres_solve(A, b, x, 100, 1e-12, "float64", workspace=ws)[0])
     x_64 = x.cpu().numpy()
     for name, tt, r, xx in (("ir_frsz2_16", t_ir, r_ir, x_ir), ("float64", t_64, r_64, x_64)):
         rrn = float(np.linalg.norm(s.b - s.A.scipy() @ xx) / np.linalg.norm(s.b))
@@ -441,7 +470,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=100)
     ap.add_argument("--micro-rows", type=int, default=1 << 24)
-    ap.add_argument("--micro-reps", type=int, default=5)
+    ap.add_argument("--micro-reps", type=int, default=10)
     ap.add_argument("--micro-formats", default="frsz2_32,frsz2_21,frsz2_16,float32,float64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--all-formats", action="store_true",
@@ -550,6 +579,10 @@ def main():
     x = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
     ws = torch.empty(cb.cbgmres_workspace_bytes(s.A.n, m, "float64") // 8 + 1, dtype=torch.float64,
                      device="cuda")
+    cpu = None
+    if not args.no_cpu and not args.no_solve:
+        log("bench: oracle CPU baseline started (whole frsz2_32 solve, one host core, in the background)")
+        cpu = CpuBaseline(s, m, tol)
 
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -616,9 +649,10 @@ def main():
                                "per_launch_bytes": 101 * args.micro_rows * z["bytes_per_value"] + 8 * args.micro_rows,
                                "avg_launch_s": z["dot_s"]}
         rec["microbench"] = {"rows": args.micro_rows, "columns": 101, "formats": mb}
-    if not args.no_cpu and r_z is not None:
-        log("bench: oracle CPU baseline (bounded sample)")
-        rec["cpu_baseline"] = cpu_baseline(s, r_z["iterations"], r_z["restarts"], m)
+    if cpu is not None and r_z is not None:
+        log("bench: waiting for the oracle CPU baseline")
+        rec["cpu_baseline"] = cpu.result(r_z["iterations"])
+        log(f"bench: oracle solve {rec['cpu_baseline']['value']:.1f} s on one core of {rec['cpu_baseline']['host_cpu']}")
     print(json.dumps(rec), flush=True)
 
 

@@ -299,20 +299,29 @@ int cbgmres_solve_precond(const cb_csr* A, const double* b, double* x, int32_t m
                           size_t workspace_bytes, double* history_host, int64_t history_cap,
                           cb_result* result_host, void* stream);
 
+/* Device workspace bytes cbgmres_ir_solve needs for (n, m, format): the
+ * inner solver's workspace plus the FP64 residual r and correction d (n
+ * values each) and a few scalars.  -1 for invalid arguments. */
+int64_t cbgmres_ir_workspace_bytes(int32_t n, int32_t m, int format);
+
 /* Mixed-precision form: FP64 iterative refinement around an inner
- * compressed-basis GMRES.  Each outer step computes r = b - A x in FP64,
- * runs one inner cycle of GMRES(m) on A d = r from d = 0 with the given basis
- * format and relative tolerance inner_tol, and adds x += d in FP64; it stops
- * when ||b - A x|| <= tol ||b|| or after max_outer steps.  Synchronous.
+ * compressed-basis GMRES (restart read as refinement, Section V-C).  Each
+ * outer step computes r = b - A x in FP64, runs one inner cycle of GMRES(m) on
+ * A d = r from d = 0 with the given basis format and relative tolerance
+ * inner_tol, and adds x += d in FP64; it stops when ||b - A x|| <= tol ||b||
+ * or after max_outer steps.  Synchronous.
+ * workspace: device memory of at least cbgmres_ir_workspace_bytes (256-byte
+ * aligned; caller-owned), or NULL and 0 for a library allocation freed before
+ * return; a smaller one gives CB_ERR_WORKSPACE.
  * result_host: iterations = inner steps in total, restarts = outer steps. */
 int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, double inner_tol,
-                     double tol, int format, int32_t max_outer, cb_result* result_host,
-                     void* stream);
+                     double tol, int format, int32_t max_outer, void* workspace,
+                     size_t workspace_bytes, cb_result* result_host, void* stream);
 
 /* ======================================================================
- * Basis format chosen before the first restart (the autotuning the paper's
- * conclusions propose, Section VIII: observe the convergence per unit time of
- * several candidate methods, then continue with the best one).
+ * Basis format chosen before the first restart (the automatic choice that
+ * Section VIII leaves open: try each candidate format briefly, score how fast
+ * its residual falls per second, and finish the solve with the winner).
  *
  * Each candidate format runs a probe -- one GMRES(probe_steps) cycle from the
  * caller's x0, capped at probe_steps Arnoldi steps -- and is scored by its
@@ -430,26 +439,30 @@ int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_opti
                         cb_result* results_host, void* stream);
 
 /* ======================================================================
- * Serving: continuous batching of solve requests on one GPU.
+ * Serving: continuous batching of solve requests on one GPU (the serving
+ * form of the method; not in the paper).
  * Requests are admitted while their device footprint fits in the HBM budget
  * (basis n*(m+1) stored bytes + CSR + work vectors); later arrivals wait in
  * FIFO order and are admitted as earlier solves finish and release memory.
- * Admitted solves run concurrently on lanes (host threads, each with its own
- * HIP stream).  Small requests (n <= 16384, m <= cbgmres_batch_max_restart())
- * go to two batch lanes: a free batch lane takes every small request waiting
- * (in arrival order, as far as the budget allows) and solves them in one
- * persistent launch of the batched solver (cbgmres_solve_batch).  Larger
- * requests go, in arrival order, to the solve lanes, each running
- * cbgmres_solve on one request.  Arrival order is kept within each kind; small
- * requests do not wait behind large ones.  The path depends on a request's
- * shape only and neither path's arithmetic depends on the other requests, so
- * a result is the same alone and in any mix.
+ * Large requests run, in arrival order, on solve lanes (host threads, each
+ * with its own HIP stream and cbgmres_solve on one request at a time).  Small
+ * requests (n <= 16384, m <= cbgmres_batch_max_restart(), the paper's six
+ * formats) go to a device-resident request loop: one persistent launch of
+ * the one-workgroup solver whose workgroups take systems from a ring of
+ * descriptors while it runs, so a small request that arrives while others are
+ * being solved joins that launch as soon as a workgroup is free.  Its CSR, b,
+ * x and Krylov basis stay in device memory for the whole solve, restarts
+ * included.  Arrival order is kept within each kind; small requests do not
+ * wait behind large ones.  The path depends on a request's shape only and
+ * neither path's arithmetic depends on the other requests, so a result is the
+ * same, bit for bit, alone and in any mix.
  * ====================================================================== */
 typedef struct cb_server cb_server;
 
-/* Create a server on `device` with an HBM budget in bytes, `lanes` solve
- * lanes for large requests (1..64) and two batch lanes.  NULL on failure
- * (cb_last_error). */
+/* Create a server on `device` with an HBM budget in bytes and `lanes` solve
+ * lanes for large requests (1..64), plus the device-resident loop for small
+ * ones (its device arena is min(budget, 4 GiB), its host staging 256 MiB of
+ * pinned memory).  NULL on failure (cb_last_error). */
 cb_server* cb_server_create(size_t hbm_budget_bytes, int device, int lanes);
 
 /* Bytes a request of this shape is charged against the budget. */
@@ -472,6 +485,12 @@ int cb_server_poll(cb_server* s, uint64_t ticket, double* x_host, cb_result* res
 
 /* Bytes currently charged against the budget, and requests waiting. */
 int cb_server_stats(cb_server* s, int64_t* charged_bytes, int32_t* queued, int32_t* running);
+
+/* The device-resident loop so far: small requests published to it, those
+ * of them served by the launch that was already running when they were
+ * published (continuous admission), and launches started.  Returns CB_OK, or
+ * the error that disabled the loop (its requests then fail with it). */
+int cb_server_ring_stats(cb_server* s, int64_t* published, int64_t* joined_running, int64_t* launches);
 
 /* Wait for every submitted solve, then free the server. */
 void cb_server_destroy(cb_server* s);

@@ -112,7 +112,8 @@ SIGNATURES = {
     "cbgmres_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
     "cbgmres_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, C.c_int, C.POINTER(cb_options),
                                 _P, _SZ, _P, _I64, C.POINTER(cb_result), _P]),
-    "cbgmres_ir_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _D, C.c_int, _I32,
+    "cbgmres_ir_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
+    "cbgmres_ir_solve": (C.c_int, [C.POINTER(cb_csr), _P, _P, _I32, _D, _D, C.c_int, _I32, _P, _SZ,
                                    C.POINTER(cb_result), _P]),
     "cb_jacobi_setup": (C.c_int, [C.POINTER(cb_csr), _P, _P]),
     "cbgmres_precond_workspace_bytes": (_I64, [_I32, _I32, _I32, C.c_int]),
@@ -136,6 +137,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_uint64)]),
     "cb_server_poll": (C.c_int, [_P, C.c_uint64, _P, C.POINTER(cb_result), _P]),
     "cb_server_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "cb_server_ring_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cb_server_destroy": (None, [_P]),
 }
 
@@ -507,15 +509,22 @@ def cbgmres_solve(A: DeviceCSR, b, x, m: int, tol: float, fmt="frsz2_32", eta: f
     return out, hist[:min(history_cap, res.iterations)]
 
 
+def cbgmres_ir_workspace_bytes(n: int, m: int, fmt) -> int:
+    return int(lib().cbgmres_ir_workspace_bytes(n, m, _fmt(fmt)))
+
+
 def cbgmres_ir_solve(A: DeviceCSR, b, x, m: int, inner_tol: float, tol: float, fmt="frsz2_16",
-                     max_outer: int = 100, stream=None, check: bool = True):
+                     max_outer: int = 100, workspace=None, stream=None, check: bool = True):
+    """Iterative refinement in place on x; workspace (optional device tensor
+    of at least cbgmres_ir_workspace_bytes) keeps the call allocation-free."""
     import torch
     _dev(x, torch.float64, "x")
     _dev(b, torch.float64, "b")
     res = cb_result()
     d = A.desc()
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     st = lib().cbgmres_ir_solve(C.byref(d), _ptr(b), _ptr(x), m, inner_tol, tol, _fmt(fmt), max_outer,
-                                C.byref(res), _stream(stream))
+                                _ptr(workspace), nbytes, C.byref(res), _stream(stream))
     if check and st not in (CB_OK, CB_ERR_NOT_CONVERGED, CB_ERR_NONFINITE):
         _check(st, "cbgmres_ir_solve")
     out = res.as_dict()
@@ -694,6 +703,13 @@ class Server:
         cb_, q, r = C.c_int64(), C.c_int32(), C.c_int32()
         _check(lib().cb_server_stats(self._h, C.byref(cb_), C.byref(q), C.byref(r)), "cb_server_stats")
         return int(cb_.value), int(q.value), int(r.value)
+
+    def ring_stats(self):
+        """(published, joined_running, launches) of the device-resident loop
+        for small requests."""
+        p, j, n = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().cb_server_ring_stats(self._h, C.byref(p), C.byref(j), C.byref(n)), "cb_server_ring_stats")
+        return int(p.value), int(j.value), int(n.value)
 
     def close(self):
         if self._h:

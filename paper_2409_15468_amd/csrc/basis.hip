@@ -35,7 +35,8 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = v[q] / d;  // IEEE division per entry
     }
-    if (v_out) store_rows<FMT>(v_out, tile0, lane, n, v);
+    __shared__ double stage[kThreads / 64][kTile];
+    if (v_out) store_rows_lds<FMT>(v_out, tile0, lane, n, v, stage[threadIdx.x >> 6]);
     const bool bad = encode_tile<FMT>(values, exps, np, tile0, lane, v, bits, bs_log);
     if (flag && bad) atomicOr(flag, 1);
 }
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double*
     else load_tiles<FMT, 1, kStream>(t, V, cols, tile0, lane);
     double out[8];
     t[0].decode(out);
-    store_rows<FMT>(x, tile0, lane, V.n, out);
+    __shared__ double stage[kThreads / 64][kTile];
+    store_rows_lds<FMT>(x, tile0, lane, V.n, out, stage[wave]);
 }
 
 // ----------------------------------------------------------------- CGS projection
@@ -125,6 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
     __shared__ double elds[kEpiLds];
     // the coefficients (written by an earlier kernel), read once into LDS
     __shared__ double hc[kMaxRestart + 1];
+    __shared__ double stage[kThreads / 64][kTile];
     for (int i = threadIdx.x; i < j; i += kThreads) hc[i] = ld_ctl(&h[i]);
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
             t = fma(wv[q], wv[q], t);  // rows >= n hold 0
         }
         nrm += t;
-        store_rows<FMT>(w, tile0, lane, V.n, wv);
+        store_rows_lds<FMT>(w, tile0, lane, V.n, wv, stage[wave]);
     }
     if (partials) {
         const double t = block_sum<kThreads>(nrm);
@@ -178,6 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int 
     __shared__ double elds[kEpiLds];
     __shared__ double hc[kMaxRestart + 1];
     __shared__ double red[kThreads / 64][kMaxRestart + 2];
+    __shared__ double stage[kThreads / 64][kTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int G = gridDim.x;
     const int ngroups = row_groups_dev(V.np);
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int 
             t = fma(wv[q], wv[q], t);  // rows >= n hold 0
         }
         nrm += t;
-        store_rows<FMT>(w, tile0, lane, V.n, wv);
+        store_rows_lds<FMT>(w, tile0, lane, V.n, wv, stage[wave]);
         if constexpr (FMT == CB_F64) {  // 4 column tiles at a time: fewer registers, same sums
             if (stream) {
                 if (full) project_tile_narrow<FMT, kFull | kStream>(V, 0, j, tile0, lane, wv, red[wave]);

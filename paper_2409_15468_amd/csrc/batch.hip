@@ -3,19 +3,19 @@
 //
 // A system of up to a few ten thousand rows cannot fill the GPU: the
 // multi-workgroup path spends most of its time in launch latency.  Here one
-// workgroup of 1024 threads runs a whole solve -- every cycle, step and
+// workgroup of 512 threads runs a whole solve -- every cycle, step and
 // restart -- with its scalars (H column, Givens rotations, g, R, y) in LDS and
 // its vectors and basis in its own device workspace, which stays in the
 // caches.  Workgroups take systems from the launch's list with an atomic
 // ticket until the list is empty, so a launch is persistent over the batch and
 // slots free up as systems finish.
 //
-// Wave w of the workgroup owns the 512-row tiles w, w + 16, w + 32, ... of
+// Wave w of the workgroup owns the 512-row tiles w, w + 8, w + 16, ... of
 // every vector, with the same lane-to-row map and the same tile codecs as the
 // multi-workgroup kernels, so stored columns have the same layout and bits.
 // Each thread reads and writes only its own rows of w and x; only the SpMV
 // reads other rows (of v), after a barrier.  All reductions run in a fixed
-// order (lane tree, then the 16 waves in index order), so a system's result
+// order (lane tree, then the 8 waves in index order), so a system's result
 // does not depend on the workgroup that solves it or on the rest of the batch.
 #include <chrono>
 #include <cmath>
@@ -57,6 +57,30 @@ struct BatchOpts {
     double eta;
     int32_t max_iters;
     int32_t literal;
+};
+
+// A serving-ring descriptor: the system's device buffers (in `it`) and the
+// host-memory copies of its inputs and output.
+struct RingDesc {
+    BatchItem it;
+    const int32_t* h_row_ptr;
+    const int32_t* h_col;
+    const double* h_val;
+    const double* h_b;
+    const double* h_x0;
+    double* h_x;
+};
+
+// The ring's control words (host memory, pinned, mapped, coherent): tail and
+// stop in cache lines of their own, then per slot the done word (sequence
+// number + 1 once the slot's result is final) and the launch that served it.
+struct RingCtl {
+    unsigned tail;
+    unsigned pad0[31];
+    unsigned stop;
+    unsigned pad1[31];
+    unsigned done[kRingSlots];
+    unsigned served_by[kRingSlots];
 };
 
 struct BatchLayout {
@@ -392,6 +416,117 @@ __global__ __launch_bounds__(kBT) void k_batch(const BatchItem* __restrict__ ite
     }
 }
 
+// ----------------------------------------------------------------- serving ring
+// A persistent launch that takes small solves from a ring of descriptors the
+// host publishes while it runs (continuous batching).  The descriptors, the
+// inputs they point to (CSR, b, x0), the output x, the results and the
+// control words live in host memory that is pinned, mapped and coherent (the
+// GPU reads it uncached over the bus); the solve itself runs out of device
+// memory.  A workgroup claims the next published descriptor with a
+// compare-and-swap on a device counter (so nothing is claimed before it is
+// published), copies the inputs into the system's device buffers, solves, writes
+// x and the result back, and raises the slot's done word (system-scope release).
+// Every wait is bounded: a workgroup leaves when the host sets `stop` and
+// nothing is left to claim, when it has found nothing to claim for
+// `idle_polls` polls in a row, or -- so that streams sharing its hardware
+// queue are not held up for long -- once the launch is older than `slice`
+// ticks of the 100 MHz real-time counter; the host relaunches while work is
+// pending.
+// Loads and stores of the ring's host memory are system-scope atomics, so
+// they bypass the GPU caches: a staging area that held an earlier system's
+// inputs is never read from a stale cache line.  Polls are relaxed (an
+// acquire at system scope would invalidate the caches on every poll); the
+// descriptor loads that follow a successful claim are issued only after the
+// claim's result has been seen.
+template <class T>
+__device__ __forceinline__ T ld_sys(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ RingDesc load_desc(const RingDesc* p) {
+    static_assert(sizeof(RingDesc) % 8 == 0, "descriptor size");
+    uint64_t raw[sizeof(RingDesc) / 8];
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(RingDesc) / 8); ++k)
+        raw[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    RingDesc d;
+    __builtin_memcpy(&d, raw, sizeof(RingDesc));
+    return d;
+}
+
+// host memory -> device memory, and back
+template <class T>
+__device__ __forceinline__ void wg_copy_in(T* __restrict__ dst, const T* __restrict__ src, int64_t count) {
+    for (int64_t i = threadIdx.x; i < count; i += kBT) dst[i] = ld_sys(src + i);
+}
+__device__ __forceinline__ void wg_copy_out(double* __restrict__ dst, const double* __restrict__ src,
+                                            int64_t count) {
+    for (int64_t i = threadIdx.x; i < count; i += kBT)
+        __hip_atomic_store(dst + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(kBT) void k_batch_ring(const RingDesc* __restrict__ descs, cb_result* results,
+                                                    RingCtl* ctl, unsigned* head, BatchOpts o, int idle_polls,
+                                                    uint64_t slice, uint32_t launch_id) {
+    __shared__ Shared S;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int got = -1;
+            int idle = 0;
+            while (idle < idle_polls && __builtin_amdgcn_s_memrealtime() - t_start < slice) {
+                const unsigned t = ld_sys(&ctl->tail);
+                const unsigned h = ld_ctl(head);
+                if (h < t) {
+                    if (atomicCAS(head, h, h + 1) == h) {
+                        got = (int)h;
+                        break;
+                    }
+                    continue;  // another workgroup took it: look again at once
+                }
+                if (ld_sys(&ctl->stop)) break;
+                __builtin_amdgcn_s_sleep(127);  // ~8k cycles between polls of the bus
+                ++idle;
+            }
+            S.item = got;
+        }
+        __syncthreads();
+        const int seq = S.item;
+        __syncthreads();
+        if (seq < 0) return;
+        const int slot = seq & (kRingSlots - 1);
+        // this CU's first-level cache may still hold lines of an earlier system
+        // that used the same device memory: drop them
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const RingDesc d = load_desc(descs + slot);
+        const BatchItem& it = d.it;
+        // inputs into the device buffers (x0 into x)
+        wg_copy_in(const_cast<int32_t*>(it.row_ptr), d.h_row_ptr, (int64_t)it.n + 1);
+        wg_copy_in(const_cast<int32_t*>(it.col), d.h_col, (int64_t)it.nnz);
+        wg_copy_in(const_cast<double*>(it.val), d.h_val, (int64_t)it.nnz);
+        wg_copy_in(const_cast<double*>(it.b), d.h_b, (int64_t)it.n);
+        wg_copy_in(it.x, d.h_x0, (int64_t)it.n);
+        __syncthreads();
+        cb_result* res = results + slot;
+        switch (it.format) {
+        case CB_F64: batch_solve<CB_F64>(it, o, res, S); break;
+        case CB_F32: batch_solve<CB_F32>(it, o, res, S); break;
+        case CB_F16: batch_solve<CB_F16>(it, o, res, S); break;
+        case CB_FRSZ2_16: batch_solve<CB_FRSZ2_16>(it, o, res, S); break;
+        case CB_FRSZ2_21: batch_solve<CB_FRSZ2_21>(it, o, res, S); break;
+        default: batch_solve<CB_FRSZ2_32>(it, o, res, S); break;
+        }
+        wg_copy_out(d.h_x, it.x, (int64_t)it.n);
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&ctl->served_by[slot], launch_id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // this thread's writes, system scope
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&ctl->done[slot], (unsigned)seq + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -399,6 +534,139 @@ double now_s() {
 }  // namespace
 
 int64_t batch_workspace_bytes(int32_t n, int32_t m, int format) { return batch_layout(n, m, format).total; }
+
+// ----------------------------------------------------------------- serving ring, host side
+struct BatchRing {
+    unsigned char* host = nullptr;  // pinned, mapped, coherent: RingCtl, descriptors, results
+    RingCtl* ctl = nullptr;
+    RingDesc* descs = nullptr;
+    cb_result* results = nullptr;
+    RingCtl* ctl_dev = nullptr;
+    RingDesc* descs_dev = nullptr;
+    cb_result* results_dev = nullptr;
+    unsigned* head = nullptr;       // device: claim counter
+    hipEvent_t ended = nullptr;     // recorded after each launch
+    bool launched = false;
+    uint32_t published = 0;         // next sequence number
+    uint32_t launches = 0;
+    std::vector<uint8_t> busy;      // slot held by an unfinished system
+    int grid = 64, idle_polls = 4096;
+    uint64_t slice = 0;             // real-time counter ticks (100 MHz)
+    BatchOpts opts{0.7071067811865476, 20000, 0};
+};
+
+BatchRing* ring_create(int grid, int idle_polls, double slice_s) {
+    BatchRing* r = new BatchRing();
+    r->grid = grid;
+    r->idle_polls = idle_polls;
+    r->slice = (uint64_t)(slice_s * 1e8);
+    r->busy.assign(kRingSlots, 0);
+    const size_t o_desc = (sizeof(RingCtl) + 255) & ~size_t(255);
+    const size_t o_res = o_desc + ((kRingSlots * sizeof(RingDesc) + 255) & ~size_t(255));
+    const size_t total = o_res + kRingSlots * sizeof(cb_result);
+    void* h = nullptr;
+    if (hipHostMalloc(&h, total, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        delete r;
+        return nullptr;
+    }
+    std::memset(h, 0, total);
+    r->host = static_cast<unsigned char*>(h);
+    void* dptr = nullptr;
+    if (hipHostGetDevicePointer(&dptr, h, 0) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&r->head), 256) != hipSuccess ||
+        hipMemset(r->head, 0, 256) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ended, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        ring_destroy(r);
+        return nullptr;
+    }
+    unsigned char* d = static_cast<unsigned char*>(dptr);
+    r->ctl = reinterpret_cast<RingCtl*>(r->host);
+    r->descs = reinterpret_cast<RingDesc*>(r->host + o_desc);
+    r->results = reinterpret_cast<cb_result*>(r->host + o_res);
+    r->ctl_dev = reinterpret_cast<RingCtl*>(d);
+    r->descs_dev = reinterpret_cast<RingDesc*>(d + o_desc);
+    r->results_dev = reinterpret_cast<cb_result*>(d + o_res);
+    return r;
+}
+
+int ring_publish(BatchRing* r, const cb_batch_item& q, const int32_t* h_row_ptr, const int32_t* h_col,
+                 const double* h_val, const double* h_b, const double* h_x0, double* h_x, uint32_t* seq) {
+    if (q.A.n < 1 || q.A.n > kBatchMaxN || q.A.nnz < 0 || q.m < 1 || q.m > kBatchMaxRestart ||
+        !(q.tol > 0.0) || !batch_format(q.format) || !q.b || !q.x || !q.workspace || !q.A.row_ptr ||
+        (q.A.nnz > 0 && (!q.A.col || !q.A.val)) || !h_row_ptr || !h_b || !h_x0 || !h_x ||
+        (q.A.nnz > 0 && (!h_col || !h_val)) || !aligned(q.x, 16) || !aligned(q.b, 16) ||
+        !aligned(q.workspace, 256) || (int64_t)q.workspace_bytes < batch_workspace_bytes(q.A.n, q.m, q.format))
+        return fail(CB_ERR_INVALID_ARG, "ring: bad system");
+    const uint32_t s = r->published;
+    const int slot = (int)(s & (kRingSlots - 1));
+    if (r->busy[slot]) return fail(CB_ERR_WORKSPACE, "ring: all %d slots busy", kRingSlots);
+    unsigned char* ws = static_cast<unsigned char*>(q.workspace);
+    const BatchLayout lay = batch_layout(q.A.n, q.m, q.format);
+    RingDesc d;
+    d.it = BatchItem{q.A.row_ptr, q.A.col, q.A.val, q.b, q.x, ws + lay.vals,
+                     frsz2_bits_of(q.format) ? reinterpret_cast<uint32_t*>(ws + lay.exps) : nullptr,
+                     reinterpret_cast<double*>(ws + lay.v), reinterpret_cast<double*>(ws + lay.w),
+                     column_bytes(q.format, q.A.n), exponent_words(q.format, q.A.n),
+                     q.A.n, q.A.nnz, q.m, q.format, q.tol};
+    d.h_row_ptr = h_row_ptr;
+    d.h_col = h_col;
+    d.h_val = h_val;
+    d.h_b = h_b;
+    d.h_x0 = h_x0;
+    d.h_x = h_x;
+    r->descs[slot] = d;
+    std::memset(&r->results[slot], 0, sizeof(cb_result));
+    __atomic_store_n(&r->ctl->done[slot], 0u, __ATOMIC_RELAXED);
+    r->busy[slot] = 1;
+    r->published = s + 1;
+    __atomic_store_n(&r->ctl->tail, s + 1, __ATOMIC_RELEASE);  // the descriptor before the count
+    *seq = s;
+    return CB_OK;
+}
+
+bool ring_poll(BatchRing* r, uint32_t seq, cb_result* res, uint32_t* launch) {
+    const int slot = (int)(seq & (kRingSlots - 1));
+    if (__atomic_load_n(&r->ctl->done[slot], __ATOMIC_ACQUIRE) != seq + 1u) return false;
+    if (res) *res = r->results[slot];
+    if (launch) *launch = r->ctl->served_by[slot];
+    r->busy[slot] = 0;
+    return true;
+}
+
+bool ring_running(BatchRing* r) {
+    return r->launched && hipEventQuery(r->ended) == hipErrorNotReady;
+}
+
+uint32_t ring_kick(BatchRing* r, hipStream_t s, int* status) {
+    *status = CB_OK;
+    if (ring_running(r)) return 0;
+    const uint32_t id = ++r->launches;
+    k_batch_ring<<<r->grid, kBT, 0, s>>>(r->descs_dev, r->results_dev, r->ctl_dev, r->head, r->opts,
+                                         r->idle_polls, r->slice, id);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(r->ended, s) != hipSuccess) {
+        *status = fail(CB_ERR_HIP, "ring launch failed");
+        return 0;
+    }
+    r->launched = true;
+    return id;
+}
+
+void ring_stop(BatchRing* r) {
+    __atomic_store_n(&r->ctl->stop, 1u, __ATOMIC_RELEASE);
+    if (r->launched) (void)hipEventSynchronize(r->ended);
+    r->launched = false;
+    __atomic_store_n(&r->ctl->stop, 0u, __ATOMIC_RELEASE);
+}
+
+void ring_destroy(BatchRing* r) {
+    if (!r) return;
+    if (r->ctl) ring_stop(r);
+    if (r->ended) (void)hipEventDestroy(r->ended);
+    if (r->head) (void)hipFree(r->head);
+    if (r->host) (void)hipHostFree(r->host);
+    delete r;
+}
 
 }  // namespace cb
 
@@ -436,8 +704,8 @@ int cbgmres_solve_batch(const cb_batch_item* items, int32_t count, const cb_opti
                         "FRSZ2 formats run through cbgmres_solve)", i);
         if ((reinterpret_cast<uintptr_t>(q.workspace) & 255) != 0)
             return fail(CB_ERR_WORKSPACE, "batch item %d: workspace not 256-byte aligned", i);
-        if (!aligned(q.x, 16) || !aligned(q.b, 8))
-            return fail(CB_ERR_INVALID_ARG, "batch item %d: x must be 16-byte and b 8-byte aligned", i);
+        if (!aligned(q.x, 16) || !aligned(q.b, 16))  // both are read in 16-byte pieces
+            return fail(CB_ERR_INVALID_ARG, "batch item %d: x and b must be 16-byte aligned", i);
         if ((int64_t)q.workspace_bytes < batch_workspace_bytes(q.A.n, q.m, q.format))
             return fail(CB_ERR_WORKSPACE, "batch item %d: workspace %zu < %lld bytes", i, q.workspace_bytes,
                         (long long)batch_workspace_bytes(q.A.n, q.m, q.format));

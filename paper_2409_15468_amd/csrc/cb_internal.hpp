@@ -42,6 +42,29 @@ constexpr int kBatchMaxN = 65536;
 constexpr int kBatchMaxRestart = 104;
 int64_t batch_workspace_bytes(int32_t n, int32_t m, int format);
 
+// Serving ring (batch.hip): a persistent one-workgroup-per-system launch that
+// takes small systems from descriptors published while it runs.
+constexpr int kRingSlots = 1024;  // descriptors in flight at most (a power of two)
+struct BatchRing;
+// Pinned/mapped/coherent control block, descriptors and results; NULL on failure.
+BatchRing* ring_create(int grid, int idle_polls, double slice_s);
+// Publish one system: q holds its device buffers (validated as for
+// cbgmres_solve_batch), the h_ pointers its inputs and the output x in
+// host memory that is pinned, mapped and coherent.  *seq receives the
+// sequence number.  CB_ERR_WORKSPACE if every slot is busy.
+int ring_publish(BatchRing* r, const cb_batch_item& q, const int32_t* h_row_ptr, const int32_t* h_col,
+                 const double* h_val, const double* h_b, const double* h_x0, double* h_x, uint32_t* seq);
+// true once system seq has finished; then *res and *launch (the launch that
+// served it) are set and its slot is free again.
+bool ring_poll(BatchRing* r, uint32_t seq, cb_result* res, uint32_t* launch);
+// Launch the ring kernel on s unless a launch is still running; returns the
+// new launch's number, or 0 if none was started.  CB status via *status.
+uint32_t ring_kick(BatchRing* r, hipStream_t s, int* status);
+bool ring_running(BatchRing* r);
+// Ask the kernel to leave once nothing is left to claim, and wait for it.
+void ring_stop(BatchRing* r);
+void ring_destroy(BatchRing* r);
+
 inline int64_t nblocks(int64_t n) { return (n + kBS - 1) / kBS; }
 inline int64_t padded_rows(int64_t n) { return nblocks(n) * kBS; }
 inline int row_groups(int64_t n) { return (int)((padded_rows(n) + kRowsPerWG - 1) / kRowsPerWG); }

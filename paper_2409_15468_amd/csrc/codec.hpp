@@ -152,6 +152,41 @@ __device__ __forceinline__ void store_rows(double* __restrict__ w, int tile0, in
     }
 }
 
+// store_rows through the wave's LDS scratch `lds` (kTile doubles): the lane's
+// values go to LDS at their tile row and come back in the float64 map, so
+// that every 16-byte store instruction of the wave writes one contiguous 1 KB
+// run of w (lane t at byte 16 t).  With the 4- and 8-row maps a direct store
+// instruction scatters 16-byte pieces 32 or 64 bytes apart over 2 or 4 KB,
+// which costs the memory pipeline 2-4 times as many cache-line visits per
+// byte stored.  Whole waves call it; only this wave touches `lds`.
+template <int FMT>
+__device__ __forceinline__ void store_rows_lds(double* __restrict__ w, int tile0, int lane, int n,
+                                               const double* wv, double* lds) {
+    using M = Map<FMT>;
+    if constexpr (M::GS == 2) {
+        store_rows<FMT>(w, tile0, lane, n, wv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < M::NG; ++k) {
+#pragma unroll
+            for (int p = 0; p < M::GS; p += 2)
+                *reinterpret_cast<double2*>(lds + M::group_row(lane, k) + p) =
+                    make_double2(wv[k * M::GS + p], wv[k * M::GS + p + 1]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        using F = Map<CB_F64>;
+        double out[8];
+#pragma unroll
+        for (int k = 0; k < F::NG; ++k) {
+            const double2 t = *reinterpret_cast<const double2*>(lds + F::group_row(lane, k));
+            out[2 * k] = t.x;
+            out[2 * k + 1] = t.y;
+        }
+        __builtin_amdgcn_wave_barrier();
+        store_rows<CB_F64>(w, tile0, lane, n, out);
+    }
+}
+
 // ----------------------------------------------------------------- reading tiles
 // Tile<FMT>: one column's data for the lane's 8 rows.
 //   load(V, col, tile0, lane, lds)  issue the loads (lds: per-wave scratch, frsz2_21)

@@ -2,21 +2,24 @@
 //
 // Requests enter a queue.  A request is admitted when its device footprint
 // (basis columns, CSR arrays, work vectors, reduction partials) fits in what
-// is left of the HBM budget.  Two kinds of lanes (host worker threads, each
-// with its own HIP stream) take admitted requests, so solves overlap on the
-// device:
-//  * solve lanes take large requests in arrival order, one at a time, and run
-//    the multi-workgroup solver on them;
-//  * batch lanes take every small request waiting (in arrival order, up to
-//    kMaxBatch, as far as the budget allows) and solve them in ONE persistent
-//    launch of the one-workgroup batched solver; small requests that arrive
-//    meanwhile are picked up by the next free batch lane.
-// Small requests never wait behind large ones for a lane (they use a few CUs
-// each).  When a solve ends its memory is returned to the budget and waiting
-// requests are admitted while the other lanes keep running.  Which path a
-// request takes depends on its own shape only, and neither path's arithmetic
-// depends on what runs beside it, so a result does not depend on the mix it
-// ran in.
+// is left of the HBM budget; admission is in arrival order within each kind.
+//  * Large requests go to solve lanes (host worker threads, each with its own
+//    HIP stream), one at a time per lane, through the multi-workgroup solver.
+//  * Small requests go to a device-resident request loop: a persistent
+//    launch of the one-workgroup solver (batch.hip, k_batch_ring) whose
+//    workgroups take systems from a ring of descriptors while it runs.  The
+//    ring thread admits small requests by budget, places each in a device
+//    arena (its CSR, b, x and Krylov workspace stay on the GPU for the whole
+//    solve, every restart included), stages its inputs in pinned host memory
+//    and publishes its descriptor; a request that arrives while the launch
+//    runs is picked up by the next free workgroup of that same launch.  The
+//    ring thread collects finished systems from their done words and returns
+//    their memory to the budget.  The launch leaves when it has been idle for
+//    a while or has run for a time slice (streams sharing its hardware queue
+//    then get their turn) and is started again while work is pending.
+// Which path a request takes depends on its own shape only, and neither
+// path's arithmetic depends on what runs beside it, so a result does not
+// depend on the mix it ran in.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -24,6 +27,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -61,6 +65,9 @@ struct cb_server {
     bool stopping = false;
     uint64_t next_ticket = 1;
     std::vector<std::thread> workers;
+    // device-resident loop for small requests (under mu)
+    int64_t ring_published = 0, ring_joined = 0, ring_launches = 0;
+    int ring_status = 0;  // CB_OK, or the error that disabled the ring
 
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -69,10 +76,17 @@ struct cb_server {
 
 namespace cb {
 
-// Requests up to this size go to the batched one-workgroup solver.
+// Requests up to this size go to the device-resident loop of the one-workgroup
+// solver.
 constexpr int32_t kSmallN = 16384;
-constexpr int kMaxBatch = 512;
-constexpr int kBatchLanes = 2;
+// The loop's launch: workgroups (systems solved at once), idle polls before a
+// workgroup leaves (~8 us apart: ~20 ms), time slice, and the host staging
+// memory for the small systems' inputs and outputs.
+constexpr int kRingGrid = 128;
+constexpr int kRingIdlePolls = 2500;
+constexpr double kRingSlice = 0.05;
+constexpr int64_t kStagingBytes = int64_t(256) << 20;
+constexpr int64_t kRingArenaMax = int64_t(4) << 30;
 
 // The batched solver runs the block-32 fixed formats only; other FRSZ2
 // requests go to the solve lanes whatever their size.
@@ -142,59 +156,23 @@ static int run_request(Request& r, hipStream_t s) {
     return st;
 }
 
-// Small requests: one allocation for all of them, one batched launch.
-// Statuses land in each request's result.
-static int run_batch(std::vector<std::shared_ptr<Request>>& rs, hipStream_t s) {
-    const int count = (int)rs.size();
-    std::vector<Placed> ps(count);
-    std::vector<int64_t> base(count);
-    int64_t total = 0;
-    for (int i = 0; i < count; ++i) {
-        ps[i] = place(*rs[i], batch_workspace_bytes(rs[i]->n, rs[i]->m, rs[i]->format));
-        base[i] = total;
-        total += ps[i].total;
-    }
-    unsigned char* mem = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void**>(&mem), (size_t)total, s) != hipSuccess)
-        return fail(CB_ERR_HIP, "device allocation of %lld bytes failed", (long long)total);
-    int st = CB_OK;
-    std::vector<cb_batch_item> items(count);
-    std::vector<cb_result> res(count);
-    for (int i = 0; i < count && st == CB_OK; ++i) {
-        const Request& r = *rs[i];
-        unsigned char* m = mem + base[i];
-        if (!upload(r, m, ps[i], s)) {
-            st = fail(CB_ERR_HIP, "input copy failed");
-            break;
-        }
-        items[i].A = csr_at(r, m, ps[i]);
-        items[i].b = reinterpret_cast<double*>(m + ps[i].b);
-        items[i].x = reinterpret_cast<double*>(m + ps[i].x);
-        items[i].workspace = m + ps[i].ws;
-        items[i].workspace_bytes = (size_t)(ps[i].total - ps[i].ws);
-        items[i].m = r.m;
-        items[i].format = r.format;
-        items[i].tol = r.tol;
-    }
-    if (st == CB_OK) {
-        const int bst = cbgmres_solve_batch(items.data(), count, nullptr, res.data(), s);
-        if (bst == CB_ERR_HIP || bst == CB_ERR_INVALID_ARG || bst == CB_ERR_WORKSPACE) st = bst;
-    }
-    for (int i = 0; i < count && st == CB_OK; ++i)
-        if (hipMemcpyAsync(rs[i]->x.data(), mem + base[i] + ps[i].x, (size_t)rs[i]->n * 8,
-                           hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = fail(CB_ERR_HIP, "result copy failed");
-    (void)hipFreeAsync(mem, s);
-    (void)hipStreamSynchronize(s);
-    for (int i = 0; i < count; ++i) {
-        rs[i]->result = st == CB_OK ? res[i] : cb_result{};
-        rs[i]->result.status = st == CB_OK ? res[i].status : st;
-    }
-    return st;
+// Under the lock: a request's end -- status, time, memory back to the budget,
+// host copies of its inputs released.
+static void finish(cb_server* S, Request& r, double t) {
+    r.t_end = t;
+    r.status = r.result.status == CB_PENDING ? CB_ERR_HIP : r.result.status;
+    r.result.status = r.status;
+    S->charged -= r.bytes;
+    S->running -= 1;
+    r.row_ptr.clear(); r.row_ptr.shrink_to_fit();
+    r.col.clear(); r.col.shrink_to_fit();
+    r.val.clear(); r.val.shrink_to_fit();
+    r.b.clear(); r.b.shrink_to_fit();
 }
 
-// Under the lock: the requests a lane of this kind may take now.
-static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_lane) {
+// Under the lock: the requests a lane of this kind may take now (at most
+// `limit`).
+static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_lane, int limit) {
     std::vector<std::shared_ptr<Request>> take;
     int64_t charged = S->charged;
     for (auto it = S->queue.begin(); it != S->queue.end();) {
@@ -208,7 +186,7 @@ static std::vector<std::shared_ptr<Request>> take_work(cb_server* S, bool batch_
         charged += (*it)->bytes;
         take.push_back(*it);
         it = S->queue.erase(it);
-        if ((int)take.size() >= (batch_lane ? kMaxBatch : 1)) break;
+        if ((int)take.size() >= limit) break;
     }
     return take;
 }
@@ -219,16 +197,17 @@ static bool has_kind(const cb_server* S, bool batch_lane) {
     return false;
 }
 
-static void worker_main(cb_server* S, bool batch_lane) {
+static void worker_main(cb_server* S) {
     (void)hipSetDevice(S->device);
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+    const bool batch_lane = false;
     for (;;) {
         std::vector<std::shared_ptr<Request>> take;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
-                take = take_work(S, batch_lane);
+                take = take_work(S, batch_lane, 1);
                 if (!take.empty()) break;
                 if (S->stopping && !has_kind(S, batch_lane)) break;
                 S->cv.wait(lk);
@@ -241,31 +220,243 @@ static void worker_main(cb_server* S, bool batch_lane) {
             }
             S->running += (int)take.size();
         }
-        if (!batch_lane) {
-            int st = run_request(*take[0], s);
-            if (st == CB_PENDING) st = CB_ERR_HIP;
-            take[0]->result.status = st;
-        } else {
-            run_batch(take, s);
-        }
+        int st = run_request(*take[0], s);
+        if (st == CB_PENDING) st = CB_ERR_HIP;
+        take[0]->result.status = st;
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            const double t = S->now();
-            for (auto& r : take) {
-                r->t_end = t;
-                r->status = r->result.status == CB_PENDING ? CB_ERR_HIP : r->result.status;
-                r->result.status = r->status;
-                S->charged -= r->bytes;
-                S->running -= 1;
-                r->row_ptr.clear(); r->row_ptr.shrink_to_fit();
-                r->col.clear(); r->col.shrink_to_fit();
-                r->val.clear(); r->val.shrink_to_fit();
-                r->b.clear(); r->b.shrink_to_fit();
-            }
+            finish(S, *take[0], S->now());
         }
         S->cv.notify_all();
     }
     (void)hipStreamDestroy(s);
+}
+
+// ----------------------------------------------------------------- the device-resident loop
+// First fit over [0, size) in 256-byte units, neighbours merged on release.
+class Arena {
+  public:
+    void init(int64_t size) {
+        free_.clear();
+        if (size > 0) free_[0] = size;
+    }
+    int64_t alloc(int64_t bytes) {
+        bytes = al256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = al256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && off + bytes == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<int64_t, int64_t> free_;
+};
+
+// Host staging of one small system: inputs, then the output x.
+struct Staged {
+    int64_t rp, ci, va, b, x0, x, total;
+};
+static Staged stage_layout(const Request& r) {
+    Staged t;
+    t.rp = 0;
+    t.ci = al256((int64_t)(r.n + 1) * 4);
+    t.va = t.ci + al256((int64_t)r.nnz * 4);
+    t.b = t.va + al256((int64_t)r.nnz * 8);
+    t.x0 = t.b + al256((int64_t)r.n * 8);
+    t.x = t.x0 + al256((int64_t)r.n * 8);
+    t.total = t.x + al256((int64_t)r.n * 8);
+    return t;
+}
+
+struct InFlight {
+    std::shared_ptr<Request> r;
+    uint32_t seq;
+    int64_t doff, dbytes, soff;
+    Staged st;
+    uint32_t launch_at_publish;  // the launch running when it was published (0: none)
+};
+
+static void fail_all_small(cb_server* S, int status) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->ring_status = status;
+}
+
+static void ring_main(cb_server* S) {
+    (void)hipSetDevice(S->device);
+    hipStream_t ks = nullptr;
+    BatchRing* ring = nullptr;
+    unsigned char* dev = nullptr;
+    unsigned char* stg = nullptr;
+    unsigned char* stg_dev = nullptr;
+    const int64_t arena_bytes = std::min<int64_t>((int64_t)S->budget, kRingArenaMax);
+    if (hipStreamCreateWithFlags(&ks, hipStreamNonBlocking) != hipSuccess ||
+        !(ring = ring_create(kRingGrid, kRingIdlePolls, kRingSlice)) ||
+        hipMalloc(reinterpret_cast<void**>(&dev), (size_t)arena_bytes) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&stg), (size_t)kStagingBytes,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&stg_dev), stg, 0) != hipSuccess) {
+        fail_all_small(S, CB_ERR_HIP);
+    }
+    Arena darena, sarena;
+    darena.init(arena_bytes);
+    sarena.init(kStagingBytes);
+    std::deque<InFlight> fl;
+    uint32_t cur_launch = 0;
+    for (;;) {
+        bool progressed = false;
+        // finished systems: results back to their requests, memory to the budget
+        for (auto it = fl.begin(); it != fl.end();) {
+            cb_result res;
+            uint32_t launch = 0;
+            if (!ring_poll(ring, it->seq, &res, &launch)) {
+                ++it;
+                continue;
+            }
+            Request& r = *it->r;
+            std::memcpy(r.x.data(), stg + it->soff + it->st.x, (size_t)r.n * 8);
+            r.result = res;
+            darena.release(it->doff, it->dbytes);
+            sarena.release(it->soff, it->st.total);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (it->launch_at_publish && launch == it->launch_at_publish) S->ring_joined += 1;
+                finish(S, r, S->now());
+            }
+            S->cv.notify_all();
+            it = fl.erase(it);
+            progressed = true;
+        }
+        // admission by budget, in arrival order
+        std::vector<std::shared_ptr<Request>> take;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stopping && !has_kind(S, true) && fl.empty()) break;
+            if (S->ring_status != CB_OK) {
+                // the loop could not be set up: fail the small requests
+                take = take_work(S, true, 1 << 30);
+                const double t = S->now();
+                for (auto& r : take) {
+                    r->t_start = t;
+                    r->result = cb_result{};
+                    r->result.status = S->ring_status;
+                    S->charged += r->bytes;
+                    S->running += 1;
+                    finish(S, *r, t);
+                }
+                take.clear();
+            } else {
+                take = take_work(S, true, kRingSlots - (int)fl.size());
+                const double t = S->now();
+                for (auto& r : take) {
+                    S->charged += r->bytes;
+                    r->t_start = t;
+                }
+                S->running += (int)take.size();
+            }
+        }
+        for (size_t i = 0; i < take.size(); ++i) {
+            auto& rp = take[i];
+            Request& r = *rp;
+            const int64_t ws = batch_workspace_bytes(r.n, r.m, r.format);
+            const Placed p = place(r, ws);
+            const Staged st = stage_layout(r);
+            const int64_t doff = darena.alloc(p.total);
+            const int64_t soff = doff < 0 ? -1 : sarena.alloc(st.total);
+            if (doff < 0 || soff < 0) {
+                // fragmented: back to the front of the queue until memory frees up
+                if (doff >= 0) darena.release(doff, p.total);
+                std::lock_guard<std::mutex> lk(S->mu);
+                for (size_t k = take.size(); k-- > i;) {
+                    S->charged -= take[k]->bytes;
+                    S->running -= 1;
+                    S->queue.push_front(take[k]);
+                }
+                break;
+            }
+            unsigned char* h = stg + soff;
+            std::memcpy(h + st.rp, r.row_ptr.data(), (size_t)(r.n + 1) * 4);
+            if (r.nnz) {
+                std::memcpy(h + st.ci, r.col.data(), (size_t)r.nnz * 4);
+                std::memcpy(h + st.va, r.val.data(), (size_t)r.nnz * 8);
+            }
+            std::memcpy(h + st.b, r.b.data(), (size_t)r.n * 8);
+            std::memcpy(h + st.x0, r.x.data(), (size_t)r.n * 8);
+            unsigned char* m = dev + doff;
+            unsigned char* hd = stg_dev + soff;
+            cb_batch_item q;
+            q.A = csr_at(r, m, p);
+            q.b = reinterpret_cast<double*>(m + p.b);
+            q.x = reinterpret_cast<double*>(m + p.x);
+            q.workspace = m + p.ws;
+            q.workspace_bytes = (size_t)(p.total - p.ws);
+            q.m = r.m;
+            q.format = r.format;
+            q.tol = r.tol;
+            uint32_t seq = 0;
+            const int pst = ring_publish(ring, q, reinterpret_cast<const int32_t*>(hd + st.rp),
+                                         reinterpret_cast<const int32_t*>(hd + st.ci),
+                                         reinterpret_cast<const double*>(hd + st.va),
+                                         reinterpret_cast<const double*>(hd + st.b),
+                                         reinterpret_cast<const double*>(hd + st.x0),
+                                         reinterpret_cast<double*>(hd + st.x), &seq);
+            if (pst != CB_OK) {
+                darena.release(doff, p.total);
+                sarena.release(soff, st.total);
+                r.result = cb_result{};
+                r.result.status = pst;
+                std::lock_guard<std::mutex> lk(S->mu);
+                finish(S, r, S->now());
+                continue;
+            }
+            const uint32_t running_launch = ring_running(ring) ? cur_launch : 0;
+            fl.push_back(InFlight{rp, seq, doff, p.total, soff, st, running_launch});
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->ring_published += 1;
+            }
+            progressed = true;
+        }
+        // a launch while systems wait (a finished launch may have left some
+        // unclaimed; a fresh one with nothing to take leaves when idle)
+        if (!fl.empty() && !ring_running(ring)) {
+            int kst = CB_OK;
+            const uint32_t id = ring_kick(ring, ks, &kst);
+            if (id) {
+                cur_launch = id;
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->ring_launches += 1;
+            }
+            if (kst != CB_OK) fail_all_small(S, kst);
+        }
+        if (!progressed) {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait_for(lk, std::chrono::microseconds(fl.empty() ? 2000 : 100));
+        }
+    }
+    if (ring) ring_destroy(ring);  // sets stop and waits for the launch
+    if (dev) (void)hipFree(dev);
+    if (stg) (void)hipHostFree(stg);
+    if (ks) (void)hipStreamDestroy(ks);
 }
 
 }  // namespace cb
@@ -293,8 +484,8 @@ cb_server* cb_server_create(size_t hbm_budget_bytes, int device, int lanes) {
     S->budget = hbm_budget_bytes;
     S->device = device;
     S->t0 = std::chrono::steady_clock::now();
-    for (int i = 0; i < lanes; ++i) S->workers.emplace_back(worker_main, S, false);
-    for (int i = 0; i < kBatchLanes; ++i) S->workers.emplace_back(worker_main, S, true);
+    for (int i = 0; i < lanes; ++i) S->workers.emplace_back(worker_main, S);
+    S->workers.emplace_back(ring_main, S);
     return S;
 }
 
@@ -357,6 +548,15 @@ int cb_server_stats(cb_server* S, int64_t* charged_bytes, int32_t* queued, int32
     if (queued) *queued = (int32_t)S->queue.size();
     if (running) *running = S->running;
     return CB_OK;
+}
+
+int cb_server_ring_stats(cb_server* S, int64_t* published, int64_t* joined_running, int64_t* launches) {
+    if (!S) return fail(CB_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (published) *published = S->ring_published;
+    if (joined_running) *joined_running = S->ring_joined;
+    if (launches) *launches = S->ring_launches;
+    return S->ring_status;
 }
 
 void cb_server_destroy(cb_server* S) {

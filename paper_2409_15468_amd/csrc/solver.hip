@@ -529,21 +529,34 @@ int cbgmres_solve_precond(const cb_csr* A, const double* b, double* x, int32_t m
     return st;
 }
 
+int64_t cbgmres_ir_workspace_bytes(int32_t n, int32_t m, int format) {
+    if (n < 1 || n > kMaxRows || m < 1 || m > kMaxRestart || !valid_format(format)) return -1;
+    return layout_of(n, m, format).total + 2 * al(padded_rows(n) * 8) + 256;
+}
+
 int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, double inner_tol,
-                     double tol, int format, int32_t max_outer, cb_result* result_host,
-                     void* stream) {
+                     double tol, int format, int32_t max_outer, void* workspace, size_t workspace_bytes,
+                     cb_result* result_host, void* stream) {
     if (int e = check_solve_args(A, b, x, m, tol, format)) return e;
     if (!(inner_tol > 0.0)) return fail(CB_ERR_INVALID_ARG, "inner_tol must be positive");
     if (max_outer < 1) return fail(CB_ERR_INVALID_ARG, "max_outer must be >= 1");
+    const int n = A->n;
+    const int64_t total = cbgmres_ir_workspace_bytes(n, m, format);
+    if (workspace && (int64_t)workspace_bytes < total)
+        return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", workspace_bytes, (long long)total);
+    if (!aligned(workspace, 256)) return fail(CB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     const double t0 = now_s();
     hipStream_t s = (hipStream_t)stream;
-    const int n = A->n;
     Ws W;
     W.L = layout_of(n, m, format);
     const int64_t vec = al(padded_rows(n) * 8);
-    void* p = nullptr;
-    CB_HIP(hipMalloc(&p, (size_t)(W.L.total + 2 * vec + 256)));
-    W.base = static_cast<unsigned char*>(p);
+    void* owned = nullptr;
+    if (workspace) {
+        W.base = static_cast<unsigned char*>(workspace);
+    } else {
+        CB_HIP(hipMalloc(&owned, (size_t)total));
+        W.base = static_cast<unsigned char*>(owned);
+    }
     double* r = reinterpret_cast<double*>(W.base + W.L.total);
     double* d = reinterpret_cast<double*>(W.base + W.L.total + vec);
     double* scal = reinterpret_cast<double*>(W.base + W.L.total + 2 * vec);
@@ -591,7 +604,7 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
     }
 done:
     (void)hipStreamSynchronize(s);
-    (void)hipFree(W.base);
+    if (owned) (void)hipFree(owned);
     acc.status = status;
     acc.seconds = now_s() - t0;
     if (result_host) *result_host = acc;

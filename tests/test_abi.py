@@ -236,3 +236,41 @@ def test_header_is_plain_c(tmp_path):
     out = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only",
                           "-I", os.path.dirname(HEADER), str(src)], capture_output=True, text=True)
     assert out.returncode == 0, out.stderr
+
+
+def test_ir_arguments_without_device_work():
+    """cbgmres_ir_solve checks its workspace (size, 256-byte alignment) and
+    scalars before any device work.  Pointers here are never dereferenced."""
+    L = cb.lib()
+    res = cb.cb_result()
+    A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    need = cb.cbgmres_ir_workspace_bytes(1000, 100, "frsz2_16")
+    assert need >= cb.cbgmres_workspace_bytes(1000, 100, "frsz2_16") + 2 * 8 * 1000
+    assert cb.cbgmres_ir_workspace_bytes(0, 100, "frsz2_16") == -1
+    assert cb.cbgmres_ir_workspace_bytes(1000, 513, "frsz2_16") == -1
+    assert cb.cbgmres_ir_workspace_bytes(1000, 100, 9) == -1
+
+    def call(ws=256, ws_bytes=need, inner_tol=1e-4, max_outer=10):
+        return L.cbgmres_ir_solve(C.byref(A), 256, 256, 100, inner_tol, 1e-12, 3, max_outer, ws, ws_bytes,
+                                  C.byref(res), None)
+    assert call(ws_bytes=need - 1) == cb.CB_ERR_WORKSPACE
+    assert call(ws=256 + 16) == cb.CB_ERR_INVALID_ARG
+    assert call(inner_tol=0.0) == cb.CB_ERR_INVALID_ARG
+    assert call(max_outer=0) == cb.CB_ERR_INVALID_ARG
+
+
+def test_batch_rejects_b_not_16_byte_aligned():
+    """The batched solver reads b in 16-byte pieces, so an 8-byte-offset b is
+    an argument error before any launch.  Pointers are never dereferenced."""
+    L = cb.lib()
+    need = cb.cbgmres_batch_workspace_bytes(1000, 30, "frsz2_21")
+    res = (cb.cb_result * 1)()
+    item = (cb.cb_batch_item * 1)()
+    item[0].A = cb.cb_csr(1000, 5000, 256, 256, 256)
+    item[0].b, item[0].x, item[0].workspace = 256 + 8, 256, 256
+    item[0].workspace_bytes = need
+    item[0].m, item[0].format, item[0].tol = 30, 4, 1e-8
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_INVALID_ARG
+    item[0].b = 256
+    item[0].x = 256 + 8
+    assert L.cbgmres_solve_batch(item, 1, None, res, None) == cb.CB_ERR_INVALID_ARG

@@ -141,3 +141,30 @@ def test_generic_and_block64_formats_are_served_by_the_solve_lanes():
         else:  # the solve lanes run cbgmres_solve itself: bit for bit
             assert res["iterations"] == ref["iterations"], r.fmt
             assert np.array_equal(x.view(np.uint64), xd.cpu().numpy().view(np.uint64)), r.fmt
+
+
+def test_small_requests_join_the_running_launch():
+    """The device-resident loop: small requests submitted one after another
+    while earlier ones are being solved are taken by the launch that is
+    already running (continuous admission, counted by cb_server_ring_stats),
+    and each result is bit for bit the one-workgroup solver's result for the
+    same system solved by itself (cbgmres_solve_batch with one item)."""
+    items = [(r, s) for r, s in requests(64) if s.A.n <= 16384 and r.m <= 104][:20]
+    assert len(items) == 20
+    srv = cb.Server(8 << 30, 0, lanes=2)
+    out = run_all(srv, items, stagger=0.003)
+    published, joined, launches = srv.ring_stats()
+    srv.close()
+    print(f"ring: {published} published, {joined} served by the launch already running, {launches} launches")
+    assert published == len(items)
+    assert joined >= len(items) // 2 and launches >= 1
+    for r, s in items:
+        x, res, _ = out[r.rid]
+        A = cb.DeviceCSR.from_host(s.A.row_ptr, s.A.col, s.A.val)
+        b = torch.from_numpy(s.b).cuda()
+        xd = torch.zeros(s.A.n, dtype=torch.float64, device="cuda")
+        ref = cb.cbgmres_solve_batch([(A, b, xd, r.m, r.tol, r.fmt)])[0]
+        torch.cuda.synchronize()
+        assert res["status"] == 0 and res["converged"], (r.rid, res)
+        assert res["iterations"] == ref["iterations"], (r.rid, res["iterations"], ref["iterations"])
+        assert np.array_equal(x.view(np.uint64), xd.cpu().numpy().view(np.uint64)), r.rid
