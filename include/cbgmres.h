@@ -175,6 +175,23 @@ int64_t cb_reduce_workspace_bytes(int32_t n, int32_t ncols);
 int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, void* work,
                    size_t work_bytes, void* stream);
 
+/* The projection of cb_cgs_project for callers that cannot allocate device
+ * memory (code under stream capture, serving loops and harnesses that forbid
+ * hipMalloc): same arguments and result, computed by the same kernels, but
+ * the reduction workspace is a fixed library-owned device array of
+ * cb_cgs_project_noalloc_max_bytes() bytes (2.0 MiB; every valid n and
+ * 1 <= j <= 513 fits), so the call allocates nothing.  The array's device
+ * address is looked up on the first call on each device (that call may make
+ * the HIP runtime load the library's code on the device); each device holds
+ * its own copy until the process ends.  The call clears the array's ticket
+ * counters itself with a fill kernel.  All calls on one device share the
+ * array: calls that may overlap on one device (different streams, or host
+ * threads without stream order) race and give wrong results; calls in one
+ * stream's order are safe.  CB_ERR_WORKSPACE if a call needed more than the
+ * fixed size; other errors as for cb_cgs_project.  Asynchronous. */
+int cb_cgs_project_noalloc(const cb_basis* V, int32_t j, const double* w, double* h, void* stream);
+int64_t cb_cgs_project_noalloc_max_bytes(void);
+
 /* Classical Gram-Schmidt update with decompression fused in (Fig. 1 step 5,
  * second half, and step 6): w[k] -= sum_{i<j} h[i] * D(v_i)[k] (1 <= j <= 513;
  * each row's correction summed over i in order, then subtracted), and, if

@@ -105,6 +105,8 @@ SIGNATURES = {
     "cb_basis_load": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P]),
     "cb_reduce_workspace_bytes": (_I64, [_I32, _I32]),
     "cb_cgs_project": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _SZ, _P]),
+    "cb_cgs_project_noalloc": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P]),
+    "cb_cgs_project_noalloc_max_bytes": (_I64, []),
     "cb_cgs_subtract": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _P, _SZ, _P]),
     "cb_basis_combine": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P]),
     "cb_spmv": (C.c_int, [C.POINTER(cb_csr), _P, _P, _P, _P, _SZ, _P]),
@@ -365,6 +367,25 @@ def cb_cgs_project(V: Basis, j: int, w, h=None, work=None, stream=None):
     _check(lib().cb_cgs_project(C.byref(d), j, _ptr(w), _ptr(h), _ptr(work), nbytes, _stream(stream)),
            "cb_cgs_project")
     return h
+
+
+def cb_cgs_project_noalloc(V: Basis, j: int, w, h, stream=None):
+    """cb_cgs_project with the library's fixed device scratch as the reduction
+    workspace: nothing is allocated (h is the caller's float64[j] device
+    tensor)."""
+    import torch
+    _dev(w, torch.float64, "w")
+    _dev(h, torch.float64, "h")
+    if not (1 <= j <= V.ncols) or w.numel() < V.n or h.numel() < j:
+        raise ValueError("bad j, w or h size")
+    d = V.desc()
+    _check(lib().cb_cgs_project_noalloc(C.byref(d), j, _ptr(w), _ptr(h), _stream(stream)),
+           "cb_cgs_project_noalloc")
+    return h
+
+
+def cb_cgs_project_noalloc_max_bytes() -> int:
+    return int(lib().cb_cgs_project_noalloc_max_bytes())
 
 
 def cb_cgs_subtract(V: Basis, j: int, h, w, norm2=None, work=None, stream=None):

@@ -2,6 +2,7 @@
 // points, plus the thread-local error text.
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 #include "cb_internal.hpp"
 #include "epilogue.hpp"
@@ -83,6 +84,41 @@ static int check_vec16(const void* a, const void* b = nullptr, const void* c = n
     if (!aligned(a, 16) || !aligned(b, 16) || !aligned(c, 16))
         return fail(CB_ERR_INVALID_ARG, "device vectors must be 16-byte aligned");
     return CB_OK;
+}
+
+// ----------------------------------------------------------------- projection without allocation
+// Reduction workspace of cb_cgs_project_noalloc: a file-scope device array
+// that covers every valid call (ticket counters, then kDotGroups partials for
+// each of up to kMaxRestart + 1 columns: 2.0 MiB).  Each GPU the library runs
+// on holds its own copy until the process ends.  Host code never names the
+// array in a launch: it takes the device address from hipGetSymbolAddress,
+// once per device, and passes that.
+constexpr int64_t kNoAllocScratchBytes = kCounterBytes + 8 * (int64_t)kDotGroups * (kMaxRestart + 1);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+// The scratch array's device address on the current device (looked up on the
+// first call there), or NULL with the error text set.
+static void* scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        fail(CB_ERR_HIP, "no usable current device (%d)", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fail(CB_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
 }
 
 }  // namespace cb
@@ -197,6 +233,28 @@ int cb_cgs_project(const cb_basis* V, int32_t j, const double* w, double* h, voi
     hipStream_t s = (hipStream_t)stream;
     launch_zero_counter(static_cast<unsigned*>(work), s);
     launch_project(V->format, *V, j, w, partials_of(work), nullptr, store_epi(h, work), s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
+int64_t cb_cgs_project_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int cb_cgs_project_noalloc(const cb_basis* V, int32_t j, const double* w, double* h, void* stream) {
+    if (int st = check_basis(V, j)) return st;
+    if (j < 1 || !w || !h) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (int st = check_vec16(w)) return st;
+    if (j > kMaxRestart + 1)
+        return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart + 1);
+    // the projection writes dot_groups(n) partials per column after the counters
+    const int64_t need = kCounterBytes + 8 * (int64_t)dot_groups(V->n) * j;
+    if (need > kNoAllocScratchBytes)
+        return fail(CB_ERR_WORKSPACE, "n=%d, j=%d needs %lld bytes of scratch, more than the fixed %lld",
+                    V->n, j, (long long)need, (long long)kNoAllocScratchBytes);
+    void* ws = scratch_on_current_device();
+    if (!ws) return CB_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    launch_zero_counter(static_cast<unsigned*>(ws), s);  // a fill kernel, no memset node
+    launch_project(V->format, *V, j, w, partials_of(ws), nullptr, store_epi(h, ws), s);
     CB_HIP(hipGetLastError());
     return CB_OK;
 }

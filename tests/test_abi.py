@@ -98,6 +98,16 @@ def test_column_count_limits_without_device_work():
     assert L.cb_cgs_project(C.byref(V), 514, 256, 256, 256, 1 << 30, None) == cb.CB_ERR_INVALID_ARG
     assert L.cb_cgs_subtract(C.byref(V), 514, 256, 256, None, None, 0, None) == cb.CB_ERR_INVALID_ARG
     assert L.cb_basis_combine(C.byref(V), 514, 256, 256, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_project_noalloc(C.byref(V), 514, 256, 256, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_project_noalloc(C.byref(V), 0, 256, 256, None) == cb.CB_ERR_INVALID_ARG
+    assert L.cb_cgs_project_noalloc(C.byref(V), 4, 256, None, None) == cb.CB_ERR_INVALID_ARG
+
+
+def test_noalloc_scratch_size():
+    """The fixed scratch of the allocation-free projection holds the ticket
+    counters and 512 workgroup partials for each of 513 columns, the most any
+    valid call writes."""
+    assert cb.cb_cgs_project_noalloc_max_bytes() == 8192 + 8 * 512 * 513
 
 
 def test_batch_arguments_without_device_work():
