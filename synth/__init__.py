@@ -74,18 +74,32 @@ def convection_diffusion(N: int, dim: int, beta, nu: float = 1.0) -> CSR:
     n = N ** dim
     idx = np.arange(n, dtype=np.int64)
     coords = [(idx // N ** a) % N for a in range(dim)]
-    rows = [idx]
-    cols = [idx]
-    vals = [np.full(n, 2.0 * dim * nu)]
-    for a in range(dim):
-        stride = N ** a
-        for sgn in (-1, 1):
-            ok = (coords[a] + sgn >= 0) & (coords[a] + sgn < N)
-            r = idx[ok]
-            rows.append(r)
-            cols.append(r + sgn * stride)
-            vals.append(np.full(r.size, -nu + sgn * beta[a] * h / 2.0))
-    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+    # the stencil's entries in increasing column order: -z, -y, -x, the
+    # diagonal, +x, +y, +z (strides N^2, N, 1), so each row comes out sorted
+    # without a sort
+    offsets = [(a, -1) for a in reversed(range(dim))] + [None] + [(a, 1) for a in range(dim)]
+    k = len(offsets)
+    cols = np.empty((n, k), dtype=np.int64)
+    vals = np.empty((n, k), dtype=np.float64)
+    keep = np.empty((n, k), dtype=bool)
+    for t, off in enumerate(offsets):
+        if off is None:
+            cols[:, t] = idx
+            vals[:, t] = 2.0 * dim * nu
+            keep[:, t] = True
+        else:
+            a, sgn = off
+            cols[:, t] = idx + sgn * N ** a
+            vals[:, t] = -nu + sgn * beta[a] * h / 2.0
+            keep[:, t] = (coords[a] + sgn >= 0) & (coords[a] + sgn < N)
+    counts = keep.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("nnz exceeds 32-bit indexing")
+    flat = keep.ravel()
+    return CSR(n, row_ptr.astype(np.int32), cols.ravel()[flat].astype(np.int32),
+               np.ascontiguousarray(vals.ravel()[flat]))
 
 
 def rhs_from_solution(A: CSR, x_star: np.ndarray) -> np.ndarray:
