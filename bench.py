@@ -127,27 +127,36 @@ def microbench(cb, torch, n, ncols, reps, formats):
         torch.cuda.synchronize()
         bv = (cb.cb_basis_column_bytes(fmt, n) + 4 * cb.cb_basis_exponent_words(fmt, n)) / n
         h = torch.empty(ncols, dtype=torch.float64, device="cuda")
-        work = torch.empty(cb.cb_reduce_workspace_bytes(n, ncols) // 8 + 1, dtype=torch.float64,
+        work = torch.empty(cb.cb_reduce_workspace_bytes(n, ncols + 1) // 8 + 1, dtype=torch.float64,
                            device="cuda")
         t_dot, m_dot = event_time(torch, lambda: cb.cb_cgs_project(V, ncols, w, h, work), reps)
         wt = w.clone()
         hs = torch.full((ncols,), 1e-3, dtype=torch.float64, device="cuda")
         n2 = torch.empty(1, dtype=torch.float64, device="cuda")
         t_upd, m_upd = event_time(torch, lambda: cb.cb_cgs_subtract(V, ncols, hs, wt, n2, work), reps)
+        # the first update fused with the second projection (one launch; the
+        # updated w feeds the next launch, which keeps the work the same)
+        wf = w.clone()
+        fo = torch.empty(ncols + 1, dtype=torch.float64, device="cuda")
+        hz = torch.full((ncols,), 1e-9, dtype=torch.float64, device="cuda")
+        t_fus, m_fus = event_time(torch, lambda: cb.cb_cgs_subtract_project(V, ncols, hz, wf, fo, work), reps)
+        del wf
         xo = torch.empty(n, dtype=torch.float64, device="cuda")
         t_dec, m_dec = event_time(torch, lambda: cb.cb_basis_load(V, 7, xo), reps * 4)
         t_enc, m_enc = event_time(torch, lambda: cb.cb_basis_store(V, 7, cols[7]), reps * 4)
         dot_bytes = ncols * n * bv + 8 * n
-        upd_bytes = ncols * n * bv + 16 * n
+        upd_bytes = ncols * n * bv + 16 * n  # also the fused update + projection's
         codec_bytes = (8 + bv) * n
         out[fmt] = {
             "bytes_per_value": bv,
             "dot_s": t_dot, "dot_GBs": dot_bytes / t_dot / 1e9, "dot_median_s": m_dot,
             "update_s": t_upd, "update_GBs": upd_bytes / t_upd / 1e9, "update_median_s": m_upd,
+            "fused_s": t_fus, "fused_GBs": upd_bytes / t_fus / 1e9, "fused_median_s": m_fus,
             "decompress_s": t_dec, "decompress_GBs": codec_bytes / t_dec / 1e9, "decompress_median_s": m_dec,
             "compress_s": t_enc, "compress_GBs": codec_bytes / t_enc / 1e9, "compress_median_s": m_enc,
         }
         log(f"microbench {fmt}: dot {out[fmt]['dot_GBs']:.0f} GB/s, update {out[fmt]['update_GBs']:.0f} GB/s, "
+            f"fused update+projection {out[fmt]['fused_GBs']:.0f} GB/s, "
             f"decompress {out[fmt]['decompress_GBs']:.0f} GB/s, compress {out[fmt]['compress_GBs']:.0f} GB/s")
         del V, work
         torch.cuda.empty_cache()
@@ -199,12 +208,16 @@ class CpuBaseline:
         }
 
 
-def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
-    """Continuous-batching server on the seeded request stream: requests are
-    submitted at their Poisson arrival times, results polled as they finish.
-    Latency = finish - submit on the server's clock."""
+def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4, standalone=False):
+    """Continuous-batching server on the seeded request stream (the first
+    `count` requests of the 512-request stream): requests are submitted at
+    their Poisson arrival times, results polled as they finish.  Latency =
+    finish - submit on the server's clock.  With `standalone`, every request is
+    then solved again on its own (one at a time through the same server) and
+    the sum of those times is reported beside the makespan: how much the mix
+    overlapped on the GPU."""
     import synth
-    reqs = synth.serving_requests(count, rate, seed)
+    reqs = synth.serving_requests(512, rate, seed)[:count]
     log(f"serving: building {count} systems")
     t = time.time()
     mats = {}
@@ -241,6 +254,18 @@ def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
                 done[pending.pop(tk)] = out
         time.sleep(0.0005)
     wall = time.perf_counter() - t0
+    alone = None
+    if standalone:
+        log("serving: each request alone")
+        alone = []
+        differ = 0
+        for i in range(count):
+            A, b = systems[i]
+            tk = server.submit(A.row_ptr, A.col, A.val, b, reqs[i].m, reqs[i].tol, reqs[i].fmt)
+            while (out := server.poll(tk, A.n)) is None:
+                time.sleep(0.0002)
+            alone.append(out[2][2] - out[2][1])
+            differ += int(not np.array_equal(out[0], done[i][0]))
     server.close()
     lat = np.array([done[i][2][2] - done[i][2][0] for i in range(count)])
     queue = np.array([done[i][2][1] - done[i][2][0] for i in range(count)])
@@ -263,6 +288,10 @@ def serving_bench(cb, torch, count, rate, budget_gb, lanes, seed=4):
            "p50_latency_small_s": float(np.percentile(lat[small], 50)) if small.any() else None,
            "p50_latency_large_s": float(np.percentile(lat[~small], 50)) if (~small).any() else None,
            "converged_within_tol": ok, "worst_rrn_over_tol": worst}
+    if alone is not None:
+        out["standalone_sum_s"] = float(sum(alone))
+        out["standalone_over_makespan"] = float(sum(alone) / (last - first))
+        out["alone_differs_from_mix"] = differ  # requests whose x alone is not bit-identical to the mix's
     log(f"serving: p50 {out['p50_latency_s'] * 1e3:.1f} ms, p99 {out['p99_latency_s'] * 1e3:.1f} ms, "
         f"{out['solves_per_s']:.1f} solves/s, {ok}/{count} within tol")
     return out
@@ -491,6 +520,12 @@ def main():
                          "format picked by probing against every fixed format; precond: Jacobi right "
                          "preconditioning on the column-scaled sweep operator")
     ap.add_argument("--serve-count", type=int, default=512)
+    ap.add_argument("--serve-leg", type=int, default=128,
+                    help="requests of the seeded serving stream run after the sweep legs of the default "
+                         "workload (0: none)")
+    ap.add_argument("--serve-standalone", action="store_true",
+                    help="serving workload: also solve every request alone and report the sum of those "
+                         "times against the makespan")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-lanes", type=int, default=8)
@@ -511,7 +546,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "serving":
-        sv = serving_bench(cb, torch, args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_lanes)
+        sv = serving_bench(cb, torch, args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_lanes,
+                           standalone=args.serve_standalone)
         rec = {"metric": "serving p50/p99 latency and solves/s", "value": sv["solves_per_s"],
                "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": sv["wall_s"] * 1e3,
                "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
@@ -649,6 +685,11 @@ def main():
                                "per_launch_bytes": 101 * args.micro_rows * z["bytes_per_value"] + 8 * args.micro_rows,
                                "avg_launch_s": z["dot_s"]}
         rec["microbench"] = {"rows": args.micro_rows, "columns": 101, "formats": mb}
+    if args.serve_leg > 0 and not args.no_solve:
+        sv = serving_bench(cb, torch, args.serve_leg, args.serve_rate, args.serve_budget_gb, args.serve_lanes)
+        rec["serving"] = dict(sv, workload=f"the first {args.serve_leg} of the 512 seeded requests (Poisson "
+                                           f"{args.serve_rate}/s, n 32^2..128^3, formats f32/frsz2_16/21/32, "
+                                           f"tol 1e-12..1e-8, m 30..100), HBM budget {args.serve_budget_gb} GB")
     if cpu is not None and r_z is not None:
         log("bench: waiting for the oracle CPU baseline")
         rec["cpu_baseline"] = cpu.result(r_z["iterations"])

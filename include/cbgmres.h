@@ -200,6 +200,16 @@ int64_t cb_cgs_project_noalloc_max_bytes(void);
 int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, double* norm2,
                     void* work, size_t work_bytes, void* stream);
 
+/* The first Gram-Schmidt update fused with the second projection (Fig. 1
+ * steps 5b, 6 and 8): w[k] -= sum_{i<j} h[i] * D(v_i)[k] (each row's
+ * correction summed over i first, then subtracted), then
+ * out[i] = sum_k D(v_i)[k] * w[k] for i < j on the updated w, and
+ * out[j] = ||w||^2 (1 <= j <= 512).  out: device float64[j + 1].  work as for
+ * cb_cgs_project with j + 1 columns.  Sums run in fixed orders that depend on
+ * (n, j) only.  Asynchronous. */
+int cb_cgs_subtract_project(const cb_basis* V, int32_t j, const double* h, double* w, double* out,
+                            void* work, size_t work_bytes, void* stream);
+
 /* Solution update with decompression fused in (Fig. 1 step 17):
  * x[k] += sum_{i<j} y[i] * D(v_i)[k] (1 <= j <= 513).  y: device float64[j].
  * Asynchronous. */

@@ -108,6 +108,7 @@ SIGNATURES = {
     "cb_cgs_project_noalloc": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P]),
     "cb_cgs_project_noalloc_max_bytes": (_I64, []),
     "cb_cgs_subtract": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _P, _SZ, _P]),
+    "cb_cgs_subtract_project": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _P, _SZ, _P]),
     "cb_basis_combine": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P]),
     "cb_spmv": (C.c_int, [C.POINTER(cb_csr), _P, _P, _P, _P, _SZ, _P]),
     "cb_residual": (C.c_int, [C.POINTER(cb_csr), _P, _P, _P, _P, _P, _SZ, _P]),
@@ -386,6 +387,26 @@ def cb_cgs_project_noalloc(V: Basis, j: int, w, h, stream=None):
 
 def cb_cgs_project_noalloc_max_bytes() -> int:
     return int(lib().cb_cgs_project_noalloc_max_bytes())
+
+
+def cb_cgs_subtract_project(V: Basis, j: int, h, w, out=None, work=None, stream=None):
+    """w -= D(V[:, :j]) h, then out[:j] = D(V[:, :j])^T w and out[j] = ||w||^2
+    (the first update fused with the second projection)."""
+    import torch
+    _dev(w, torch.float64, "w")
+    _dev(h, torch.float64, "h")
+    if not (1 <= j <= V.ncols) or w.numel() < V.n or h.numel() < j:
+        raise ValueError("bad j, w or h size")
+    if out is None:
+        out = torch.empty(j + 1, dtype=torch.float64, device=w.device)
+    if work is None:
+        work, nbytes = _work(V.n, j + 1, w.device)
+    else:
+        nbytes = work.numel() * work.element_size()
+    d = V.desc()
+    _check(lib().cb_cgs_subtract_project(C.byref(d), j, _ptr(h), _ptr(w), _ptr(out), _ptr(work), nbytes,
+                                         _stream(stream)), "cb_cgs_subtract_project")
+    return out
 
 
 def cb_cgs_subtract(V: Basis, j: int, h, w, norm2=None, work=None, stream=None):

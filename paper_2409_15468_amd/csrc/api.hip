@@ -277,6 +277,23 @@ int cb_cgs_subtract(const cb_basis* V, int32_t j, const double* h, double* w, do
     return CB_OK;
 }
 
+int cb_cgs_subtract_project(const cb_basis* V, int32_t j, const double* h, double* w, double* out,
+                            void* work, size_t work_bytes, void* stream) {
+    if (int st = check_basis(V, j)) return st;
+    if (j < 1 || !w || !h || !out || !work) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");
+    if (int st = check_vec16(w)) return st;
+    if (j > kMaxRestart)
+        return fail(CB_ERR_INVALID_ARG, "j=%d columns exceeds the limit of %d", j, kMaxRestart);
+    if ((int64_t)work_bytes < reduce_workspace_bytes(V->n, j + 1, 0))
+        return fail(CB_ERR_WORKSPACE, "workspace %zu < %lld bytes", work_bytes,
+                    (long long)reduce_workspace_bytes(V->n, j + 1, 0));
+    hipStream_t s = (hipStream_t)stream;
+    launch_zero_counter(static_cast<unsigned*>(work), s);
+    launch_subtract_project(V->format, *V, j, h, w, partials_of(work), nullptr, store_epi(out, work), s);
+    CB_HIP(hipGetLastError());
+    return CB_OK;
+}
+
 int cb_basis_combine(const cb_basis* V, int32_t j, const double* y, double* x, void* stream) {
     if (int st = check_basis(V, j)) return st;
     if (j < 1 || !y || !x) return fail(CB_ERR_INVALID_ARG, "bad j or NULL pointer");

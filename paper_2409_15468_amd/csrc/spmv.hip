@@ -22,31 +22,81 @@ using namespace dev;
 
 // y = A x over the row blocks blk = blockIdx.x, +gridDim.x, ... of 256/LPR rows
 // (x[c] read as xs[c] / d when DIV: the normalised vector formed on the fly);
-// returns this thread's share of ||y||^2.
-template <int LPR, bool DIV>
+// with b != NULL the result is b - A x.  Returns this thread's share of
+// ||y||^2.  Lane li of a row's group of LPR lanes accumulates the row's
+// entries li, li + LPR, ... with FMA in CSR order, then the group sums with a
+// fixed shuffle tree.  The loads are what limits a row: row pointer, then
+// column index and value, then the x gather, each waiting on the one before.
+// So each group works on U row blocks at once and issues the loads of every
+// level for all U rows (the first two entries per lane, unconditionally, with
+// clamped indices) before it waits; entries past 2 LPR in a row, if any, follow
+// in a loop.  The sums are the same, in the same order, as one row at a time.
+template <int LPR, bool DIV, int U = 4>
 __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                             const double* __restrict__ val, const double* __restrict__ xs,
-                                            double d, double* __restrict__ y) {
+                                            double d, const double* __restrict__ b, double* __restrict__ y) {
     constexpr int RPW = 256 / LPR;
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
     const int nblk = (n + RPW - 1) / RPW;
+    const int G = gridDim.x;
     double nrm = 0.0;
-    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int row = blk * RPW + sub;
-        double s = 0.0;
-        if (row < n) {
-            const int k1 = rp[row + 1];
-            for (int k = rp[row] + li; k < k1; k += LPR) {
-                const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
-                s = fma(val[k], xv, s);
+    if (__builtin_amdgcn_readfirstlane(rp[n]) == 0) {  // no entries at all: y = b or 0
+        for (int blk = blockIdx.x; blk < nblk; blk += G) {
+            const int row = blk * RPW + sub;
+            if (row < n && li == 0) {
+                const double t = b ? b[row] : 0.0;
+                y[row] = t;
+                nrm = fma(t, t, nrm);
             }
         }
+        return nrm;
+    }
+    for (int blk0 = blockIdx.x; blk0 < nblk; blk0 += U * G) {
+        int row[U], k0[U], k1[U];
 #pragma unroll
-        for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-        if (row < n && li == 0) {
-            y[row] = s;
-            nrm = fma(s, s, nrm);
+        for (int u = 0; u < U; ++u) {
+            row[u] = (blk0 + u * G) * RPW + sub;  // rows >= n have no entries
+            const int r = min(row[u], n);
+            k0[u] = rp[r];
+            k1[u] = rp[min(row[u] + 1, n)];
+        }
+        int c[U][2];
+        double v[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = k0[u] + li + e * LPR;
+                const int kk = k < k1[u] ? k : 0;  // a real entry, or entry 0 (dropped below)
+                c[u][e] = ci[kk];
+                v[u][e] = val[kk];
+            }
+        }
+        double xv[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) xv[u][e] = xs[c[u][e]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (k0[u] + li + e * LPR < k1[u]) s = fma(v[u][e], DIV ? xv[u][e] / d : xv[u][e], s);
+            }
+            for (int k = k0[u] + li + 2 * LPR; k < k1[u]; k += LPR) {
+                const double xk = DIV ? xs[ci[k]] / d : xs[ci[k]];
+                s = fma(val[k], xk, s);
+            }
+#pragma unroll
+            for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+            if (row[u] < n && li == 0) {
+                if (b) s = b[row[u]] - s;
+                y[row[u]] = s;
+                nrm = fma(s, s, nrm);
+            }
         }
     }
     return nrm;
@@ -135,13 +185,13 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
     __shared__ double prod[4][kStagedMax];
     switch (lpr) {
     case 0: nrm = spmv_rows_staged<true>(n, rp, ci, val, w, d, nullptr, y, prod[threadIdx.x >> 6]); break;
-    case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, y); break;
-    case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, y); break;
-    case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, y); break;
-    case 8: nrm = spmv_rows<8, true>(n, rp, ci, val, w, d, y); break;
-    case 16: nrm = spmv_rows<16, true>(n, rp, ci, val, w, d, y); break;
-    case 32: nrm = spmv_rows<32, true>(n, rp, ci, val, w, d, y); break;
-    default: nrm = spmv_rows<64, true>(n, rp, ci, val, w, d, y); break;
+    case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    case 8: nrm = spmv_rows<8, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    case 16: nrm = spmv_rows<16, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    case 32: nrm = spmv_rows<32, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    default: nrm = spmv_rows<64, true>(n, rp, ci, val, w, d, nullptr, y); break;
     }
     const double t = block_sum<256>(nrm);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -173,27 +223,8 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
                                               double* __restrict__ partials, int mode,
                                               const int* __restrict__ guard) {
     if (guard && ld_ctl(guard) == 0) return;
-    constexpr int RPW = 256 / LPR;
-    const int sub = threadIdx.x / LPR;
-    const int li = threadIdx.x % LPR;
-    const int nblk = (n + RPW - 1) / RPW;
-    double nrm = 0.0;
     // row blocks blockIdx.x, blockIdx.x + gridDim.x, ... (the grid depends on n only)
-    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int row = blk * RPW + sub;
-        double s = 0.0;
-        if (row < n) {
-            const int k1 = rp[row + 1];
-            for (int k = rp[row] + li; k < k1; k += LPR) s = fma(val[k], x[ci[k]], s);
-        }
-#pragma unroll
-        for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-        if (row < n && li == 0) {
-            const double out = mode ? b[row] - s : s;
-            y[row] = out;
-            nrm = fma(out, out, nrm);
-        }
-    }
+    const double nrm = spmv_rows<LPR, false>(n, rp, ci, val, x, 1.0, mode ? b : nullptr, y);
     if (partials) {
         const double t = block_sum<256>(nrm);
         if (threadIdx.x == 0) partials[blockIdx.x] = t;
