@@ -189,7 +189,7 @@ __device__ __forceinline__ void store_rows_lds(double* __restrict__ w, int tile0
 
 // ----------------------------------------------------------------- reading tiles
 // Tile<FMT>: one column's data for the lane's 8 rows.
-//   load(V, col, tile0, lane, lds)  issue the loads (lds: per-wave scratch, frsz2_21)
+//   load(V, col, tile0, lane)       issue the loads
 //   dot(w)                          sum_q D(v)[q] * w[q]
 //   axpy(h, acc)                    acc[q] += h * D(v)[q]
 //   decode(out)                     out[q] = D(v)[q]
@@ -336,26 +336,45 @@ template <> struct Tile<CB_FRSZ2_16_B64> : Frsz2Tile16<6> {};
 
 // frsz2_21.  The lane's 8 values 8t .. 8t+7 are codes 8s .. 8s+7 (s = t % 4)
 // of block t / 4 of the tile; they start at bit 168 s = 32 (5 s) + 8 s of the
-// block, so the lane reads the block's words 5s .. 5s+5 and shifts the 6-word
+// block, so the lane needs the block's words 5s .. 5s+5 and shifts the 6-word
 // window right by 8 s bits; code q then sits at bit 21 q of the window.  The
-// wave's six word loads together cover the tile's 1344 contiguous bytes.
+// tile's codes are 1344 contiguous bytes (16-byte aligned): the wave loads them
+// as 84 pieces of 16 bytes (lane t: pieces t and 64 + t), two load
+// instructions instead of six word loads per lane, and hands them to the lanes
+// that need them through a per-wave slot of LDS when the codes are used.
+// Whole waves call dot, axpy and decode.
+__shared__ uint32_t xch21[8][336];  // one 1344-byte tile per wave, 8 waves at most
+
 template <>
 struct Tile<CB_FRSZ2_21> {
-    uint32_t y[6];
+    uint4 a, b;  // pieces lane and 64 + lane of the tile (b: lanes < 20)
     uint32_t e;
-    uint32_t s;
+    bool live;
     template <int LM>
     __device__ __forceinline__ void load(const BasisView& V, int col, int tile0, int lane) {
-        const uint32_t* base = reinterpret_cast<const uint32_t*>(V.values + (int64_t)col * V.col_bytes);
+        const unsigned char* base = V.values + (int64_t)col * V.col_bytes + (int64_t)(tile0 >> 5) * 84;
+        // bytes of whole blocks below np (a piece that straddles their end
+        // stays inside the column's 256-byte-rounded storage)
+        const int vbytes = (LM & kFull) ? 1344 : min(max((V.np - tile0) >> 5, 0), 16) * 84;
+        a = 16 * lane < vbytes ? ld16<(LM & kStream) != 0>(base + 16 * lane) : make_uint4(0, 0, 0, 0);
+        b = (lane < 20 && 1024 + 16 * lane < vbytes) ? ld16<(LM & kStream) != 0>(base + 1024 + 16 * lane)
+                                                      : make_uint4(0, 0, 0, 0);
         const int r = tile0 + 8 * lane;
-        const bool live = (LM & kFull) || r < V.np;
-        const uint32_t* p = base + (int64_t)(r >> 5) * 21 + 5 * (lane & 3);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) y[k] = live ? ld4<(LM & kStream) != 0>(p + k) : 0u;
+        live = (LM & kFull) || r < V.np;
         e = live ? V.exps[(int64_t)col * V.exp_stride + (r >> 5)] : 0u;
-        s = 8u * (lane & 3);
     }
     __device__ __forceinline__ void codes(uint32_t* c) const {
+        const int lane = threadIdx.x & 63;
+        uint32_t* x = xch21[threadIdx.x >> 6];
+        __builtin_amdgcn_wave_barrier();  // the slot's previous tile has been read
+        *reinterpret_cast<uint4*>(x + 4 * lane) = a;
+        if (lane < 20) *reinterpret_cast<uint4*>(x + 256 + 4 * lane) = b;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t* p = x + (lane >> 2) * 21 + 5 * (lane & 3);
+        uint32_t y[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) y[k] = live ? p[k] : 0u;
+        const uint32_t s = 8u * (lane & 3);
         uint32_t z[6];
 #pragma unroll
         for (int k = 0; k < 5; ++k) z[k] = __builtin_amdgcn_alignbit(y[k + 1], y[k], s);
