@@ -82,6 +82,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def solve_algorithmic_bytes(cb, n, nnz, fmt, res):
+    """Compulsory HBM bytes of one solve, from its own counts: every basis
+    pass (the solver's basis_bytes, which counts the columns' code bytes, scaled
+    to include the block exponents), the CSR once per SpMV (each Arnoldi step
+    and each cycle's residual), and the FP64 vectors each launch must read or
+    write (per step: the SpMV's x and y, the projection's w, the update's w in
+    and out; with the second Gram-Schmidt pass its projection's w and update's
+    w in and out; per cycle: the residual's x, b and r and the x update's x
+    in and out)."""
+    codes = cb.cb_basis_column_bytes(fmt, n)
+    withexp = codes + 4 * cb.cb_basis_exponent_words(fmt, n)
+    it, cyc, ro = res["iterations"], res["restarts"], res["reorths"]
+    csr = 12 * nnz + 4 * (n + 1)
+    basis = res["basis_bytes"] * withexp / codes
+    vectors = it * 40 * n + ro * 24 * n + (cyc + 1) * 40 * n
+    return basis + (it + cyc + 1) * csr + vectors
+
+
 def timed_solves(cb, torch, A, b, x, fmt, m, tol, steps, warmup, ws):
     res = None
     for _ in range(warmup):
@@ -347,6 +365,10 @@ def precision_bench(cb, torch, steps, warmup):
         out[name] = {"seconds": tt, "iterations": r["iterations"], "outer_or_cycles": r["restarts"],
                      "converged": bool(r["converged"]), "rel_residual": rrn,
                      "err_vs_xstar": float(np.linalg.norm(xx - s.x_star) / np.linalg.norm(s.x_star))}
+        if name == "float64":
+            by = solve_algorithmic_bytes(cb, s.A.n, s.A.nnz, "float64", r)
+            out[name]["algorithmic_bytes"] = by
+            out[name]["roofline_frac"] = by / tt / 1e9 / HBM_PEAK_GBS
         log(f"precision {name}: {tt * 1e3:.1f} ms, {r['iterations']} iterations, rrn {rrn:.2e}")
     out["err_ir_vs_float64_solve"] = float(np.linalg.norm(x_ir - x_64) / np.linalg.norm(x_64))
     out["speedup_ir_vs_float64"] = t_64 / t_ir
@@ -647,6 +669,16 @@ def main():
         x64 = x.cpu().numpy()
         log(f"bench: float64 {t_d * 1e3:.1f} ms, {r_d['iterations']} iters")
         rec.update({"value": t_z, "ms_per_step": t_z * 1e3})
+        by_z = solve_algorithmic_bytes(cb, s.A.n, s.A.nnz, "frsz2_32", r_z)
+        by_d = solve_algorithmic_bytes(cb, s.A.n, s.A.nnz, "float64", r_d)
+        rec["solve_roofline"] = {
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "frsz2_32": {"bytes": by_z, "achieved": by_z / t_z / 1e9, "frac": by_z / t_z / 1e9 / HBM_PEAK_GBS},
+            "float64": {"bytes": by_d, "achieved": by_d / t_d / 1e9, "frac": by_d / t_d / 1e9 / HBM_PEAK_GBS},
+            "note": "algorithmic bytes of the whole solve (basis passes, CSR per SpMV, FP64 vectors) over its "
+                    "time; passes the Infinity Cache serves count as HBM bytes"}
+        log(f"bench: solve-level fraction of the HBM roofline: frsz2_32 {rec['solve_roofline']['frsz2_32']['frac']:.2f}, "
+            f"float64 {rec['solve_roofline']['float64']['frac']:.2f}")
         rec["solve"] = {
             "frsz2_32": {"seconds": t_z, "iterations": r_z["iterations"], "cycles": r_z["restarts"],
                          "reorths": r_z["reorths"], "rel_residual": rel, "err_vs_xstar": err,

@@ -226,14 +226,23 @@ typedef struct cb_csr {
     const double* val;      /* device, nnz */
 } cb_csr;
 
+/* Workspace bytes of cb_spmv / cb_residual for a matrix of n rows and nnz
+ * entries: the norm's partial sums, and for rows of more than 8 entries on
+ * average the column window of every 256-row block (with it, such a SpMV
+ * stages each block's window of x in LDS instead of gathering x from memory;
+ * the results are the same).  -1 on a bad size. */
+int64_t cb_spmv_workspace_bytes(int32_t n, int32_t nnz);
+
 /* y = A x (Fig. 1 step 3, M = I) and, if norm2 != NULL, *norm2 = ||y||^2
- * (step 4); the norm needs a device workspace of 8 * (n + 1) bytes.  Column
- * indices must lie in [0, n).  Asynchronous. */
+ * (step 4).  The norm needs a device workspace of at least 8 * (n + 1) bytes;
+ * a workspace of cb_spmv_workspace_bytes(n, nnz) bytes (8-byte aligned) also
+ * lets long rows use the windowed gather, the plan being formed in it by the
+ * call.  Column indices must lie in [0, n).  Asynchronous. */
 int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
             size_t work_bytes, void* stream);
 
-/* r = b - A x and, if norm2 != NULL, *norm2 = ||r||^2 (Fig. 1 step 1).
- * Asynchronous. */
+/* r = b - A x and, if norm2 != NULL, *norm2 = ||r||^2 (Fig. 1 step 1);
+ * workspace as for cb_spmv.  Asynchronous. */
 int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, double* norm2,
                 void* work, size_t work_bytes, void* stream);
 

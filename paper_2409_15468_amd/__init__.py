@@ -110,6 +110,7 @@ SIGNATURES = {
     "cb_cgs_subtract": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _P, _SZ, _P]),
     "cb_cgs_subtract_project": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P, _P, _SZ, _P]),
     "cb_basis_combine": (C.c_int, [C.POINTER(cb_basis), _I32, _P, _P, _P]),
+    "cb_spmv_workspace_bytes": (_I64, [_I32, _I32]),
     "cb_spmv": (C.c_int, [C.POINTER(cb_csr), _P, _P, _P, _P, _SZ, _P]),
     "cb_residual": (C.c_int, [C.POINTER(cb_csr), _P, _P, _P, _P, _P, _SZ, _P]),
     "cbgmres_workspace_bytes": (_I64, [_I32, _I32, C.c_int]),
@@ -461,31 +462,37 @@ class DeviceCSR:
                       self.val.data_ptr())
 
 
-def _spmv_work(A: DeviceCSR, device):
+def cb_spmv_workspace_bytes(n: int, nnz: int) -> int:
+    return int(lib().cb_spmv_workspace_bytes(n, nnz))
+
+
+def _spmv_work(A: DeviceCSR, device, plan=True):
+    """The SpMV workspace: with plan, large enough for the windowed long-row
+    gather; without, only the norm's partial sums."""
     import torch
-    nbytes = 8 * (A.n + 1)
-    return torch.empty(nbytes // 8, dtype=torch.float64, device=device), nbytes
+    nbytes = max(8 * (A.n + 1), cb_spmv_workspace_bytes(A.n, A.nnz)) if plan else 8 * (A.n + 1)
+    return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device), nbytes
 
 
-def cb_spmv(A: DeviceCSR, x, y=None, norm2=None, stream=None):
+def cb_spmv(A: DeviceCSR, x, y=None, norm2=None, stream=None, plan=True):
     import torch
     _dev(x, torch.float64, "x")
     if y is None:
         y = torch.empty(A.n, dtype=torch.float64, device=x.device)
-    work, nbytes = _spmv_work(A, x.device)
+    work, nbytes = _spmv_work(A, x.device, plan)
     d = A.desc()
     _check(lib().cb_spmv(C.byref(d), _ptr(x), _ptr(y), _ptr(norm2), _ptr(work), nbytes, _stream(stream)),
            "cb_spmv")
     return y
 
 
-def cb_residual(A: DeviceCSR, b, x, r=None, norm2=None, stream=None):
+def cb_residual(A: DeviceCSR, b, x, r=None, norm2=None, stream=None, plan=True):
     import torch
     _dev(x, torch.float64, "x")
     _dev(b, torch.float64, "b")
     if r is None:
         r = torch.empty(A.n, dtype=torch.float64, device=x.device)
-    work, nbytes = _spmv_work(A, x.device)
+    work, nbytes = _spmv_work(A, x.device, plan)
     d = A.desc()
     _check(lib().cb_residual(C.byref(d), _ptr(b), _ptr(x), _ptr(r), _ptr(norm2), _ptr(work), nbytes,
                              _stream(stream)), "cb_residual")

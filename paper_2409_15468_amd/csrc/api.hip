@@ -313,36 +313,48 @@ static int check_csr(const cb_csr* A) {
     return CB_OK;
 }
 
-int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
-            size_t work_bytes, void* stream) {
-    if (int st = check_csr(A)) return st;
-    if (!x || !y) return fail(CB_ERR_INVALID_ARG, "NULL vector");
+// cb_spmv / cb_residual workspace: the norm's partial sums, then (rows of more
+// than 8 entries on average) the column windows of the 256-row blocks.
+static int64_t spmv_partials_bytes(const cb_csr* A) { return (8 * (int64_t)spmv_groups(A->n, A->nnz) + 255) & ~int64_t(255); }
+
+int64_t cb_spmv_workspace_bytes(int32_t n, int32_t nnz) {
+    if (bad_n(n) || nnz < 0) return -1;
+    cb_csr A{n, nnz, nullptr, nullptr, nullptr};
+    return spmv_partials_bytes(&A) + (spmv_uses_plan(n, nnz) ? spmv_plan_bytes(n) : 0);
+}
+
+static int spmv_common(const cb_csr* A, const double* x, const double* b, double* y, double* norm2, void* work,
+                       size_t work_bytes, int mode, void* stream) {
     const int G = spmv_groups(A->n, A->nnz);
     const int64_t need = 8 * (int64_t)G;
     if (norm2 && (!work || (int64_t)work_bytes < need))
         return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
     hipStream_t s = (hipStream_t)stream;
     double* part = norm2 ? static_cast<double*>(work) : nullptr;
-    launch_spmv(*A, x, nullptr, y, part, 0, nullptr, s);
+    void* plan = nullptr;
+    if (work && spmv_uses_plan(A->n, A->nnz) &&
+        (int64_t)work_bytes >= cb_spmv_workspace_bytes(A->n, A->nnz) && aligned(work, 8)) {
+        plan = static_cast<unsigned char*>(work) + spmv_partials_bytes(A);
+        launch_spmv_plan(*A, plan, s);
+    }
+    launch_spmv(*A, x, b, y, part, mode, nullptr, s, plan);
     if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
     CB_HIP(hipGetLastError());
     return CB_OK;
+}
+
+int cb_spmv(const cb_csr* A, const double* x, double* y, double* norm2, void* work,
+            size_t work_bytes, void* stream) {
+    if (int st = check_csr(A)) return st;
+    if (!x || !y) return fail(CB_ERR_INVALID_ARG, "NULL vector");
+    return spmv_common(A, x, nullptr, y, norm2, work, work_bytes, 0, stream);
 }
 
 int cb_residual(const cb_csr* A, const double* b, const double* x, double* r, double* norm2,
                 void* work, size_t work_bytes, void* stream) {
     if (int st = check_csr(A)) return st;
     if (!x || !r || !b) return fail(CB_ERR_INVALID_ARG, "NULL vector");
-    const int G = spmv_groups(A->n, A->nnz);
-    const int64_t need = 8 * (int64_t)G;
-    if (norm2 && (!work || (int64_t)work_bytes < need))
-        return fail(CB_ERR_WORKSPACE, "norm needs a workspace of %lld bytes", (long long)need);
-    hipStream_t s = (hipStream_t)stream;
-    double* part = norm2 ? static_cast<double*>(work) : nullptr;
-    launch_spmv(*A, x, b, r, part, 1, nullptr, s);
-    if (norm2) launch_reduce(part, G, 1, norm2, 0, nullptr, s);
-    CB_HIP(hipGetLastError());
-    return CB_OK;
+    return spmv_common(A, x, b, r, norm2, work, work_bytes, 1, stream);
 }
 
 }  // extern "C"

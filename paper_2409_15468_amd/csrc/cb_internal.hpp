@@ -170,13 +170,19 @@ void launch_reduce(const double* partials, int G, int ncols, double* out, int op
                    const int* guard, hipStream_t s);
 // y = A x (mode 0) or y = b - A x (mode 1); with partials != NULL also
 // ||y||^2 per workgroup (spmv_groups of them, summed by the consumer).
+// plan (optional, from launch_spmv_plan): per 256-row block the range of
+// columns, so that rows longer than 8 entries on average gather x from LDS.
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
-                 int mode, const int* guard, hipStream_t s);
+                 int mode, const int* guard, hipStream_t s, const void* plan = nullptr);
+// The SpMV plan: bytes, whether the matrix's SpMV uses it, and its kernel.
+int64_t spmv_plan_bytes(int32_t n);
+bool spmv_uses_plan(int32_t n, int32_t nnz);
+void launch_spmv_plan(const cb_csr& A, void* plan, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
 // Column col := Q(w / *divisor) and y = A (w / *divisor), ||y||^2 partials
 // (spmv_groups of them); flag (device, required) set on a non-finite store.
 void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, const double* w,
                        const double* divisor, double* y, double* partials, int32_t* flag, const int* guard,
-                       hipStream_t s);
+                       hipStream_t s, const void* plan = nullptr);
 
 }  // namespace cb

@@ -35,7 +35,7 @@ namespace cb {
 using namespace dev;
 
 struct Layout {
-    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, w2, vals, exps, part, part_s, total;
+    int64_t state, flag, counter, H, cs, sn, g, u, y, hist, w, w2, vals, exps, part, part_s, plan, total;
 };
 
 static int64_t al(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -65,6 +65,7 @@ static Layout layout_of(int32_t n, int32_t m, int fmt) {
     if (np_ < kSpmvGroups) np_ = kSpmvGroups;
     L.part = take(8 * np_);
     L.part_s = take(8 * (int64_t)kSpmvGroups);  // SpMV partials: one per SpMV workgroup
+    L.plan = take(spmv_plan_bytes(n));           // SpMV column windows (rows of > 8 entries)
     L.total = off;
     return L;
 }
@@ -248,7 +249,7 @@ static void enqueue_sumsq(const double* x, int n, double* part, double* dst, hip
 static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double tol, int fmt,
                       const cb_options* opt, const Ws& W, double* history_host,
                       int64_t history_cap, cb_result* res, hipStream_t s,
-                      const double* dinv = nullptr, const double* pval = nullptr) {
+                      const double* dinv = nullptr, const double* pval = nullptr, bool plan_ready = false) {
     const double t0 = now_s();
     const int n = A.n;
     const double eta = (opt && opt->eta > 0) ? opt->eta : 0.7071067811865476;
@@ -274,6 +275,13 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     const int Gs = spmv_groups(n, A.nnz);
     cb_csr AM = A;  // the operator of the Arnoldi steps: A, or A M^-1
     if (dinv) AM.val = pval;
+    // column windows of the matrix's row blocks for the long-row SpMV (A and
+    // A M^-1 share the pattern)
+    void* plan = nullptr;
+    if (spmv_uses_plan(n, A.nnz)) {
+        plan = W.base + W.L.plan;
+        if (!plan_ready) launch_spmv_plan(A, plan, s);  // else the caller formed it in this workspace
+    }
     cb_basis V{fmt, n, m + 1, 0, W.base + W.L.vals,
                frsz2_bits_of(fmt) ? W.at<uint32_t>(W.L.exps) : nullptr};
     const double cbytes = (double)column_bytes(fmt, n);
@@ -316,7 +324,7 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
         int prev_iters = 0, prev_reorths = 0;
         for (;;) {
             // restart: explicit residual into w, beta, stop test
-            launch_spmv(A, x, b, w, part_s, 1, nullptr, s);
+            launch_spmv(A, x, b, w, part_s, 1, nullptr, s, plan);
             k_cycle_begin<<<1, 256, 0, s>>>(st, flag, g, m, part_s, Gs);
             CB_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
             if (cycles > 0) CB_HIP(hipMemcpyAsync(hh, hist, (size_t)m * 8, hipMemcpyDeviceToHost, s));
@@ -348,7 +356,8 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 double* hcol = H + (int64_t)j * (m + 1);
                 // v_j = w / (beta or h_{j,j-1}), V_j = Q(v_j), w = A v_j; its
                 // ||w||^2 partials go to the first update's epilogue
-                launch_spmv_store(fmt, AM, V, j, wc, j == 0 ? &st->beta : &st->hn, wn, part_s, flag, active, s);
+                launch_spmv_store(fmt, AM, V, j, wc, j == 0 ? &st->beta : &st->hn, wn, part_s, flag, active, s,
+                                  plan);
                 double* t = wc;
                 wc = wn;
                 wn = t;
@@ -580,8 +589,10 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
         status = CB_OK;
         goto done;
     }
+    if (spmv_uses_plan(n, A->nnz)) launch_spmv_plan(*A, W.base + W.L.plan, s);
     for (;;) {
-        launch_spmv(*A, x, b, r, part, 1, nullptr, s);
+        launch_spmv(*A, x, b, r, part, 1, nullptr, s,
+                    spmv_uses_plan(n, A->nnz) ? W.base + W.L.plan : nullptr);
         launch_reduce(part, spmv_groups(n, A->nnz), 1, scal, 0, nullptr, s);
         if (hipMemcpyAsync(hv, scal, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { status = fail(CB_ERR_HIP, "copy failed"); goto done; }
@@ -592,7 +603,8 @@ int cbgmres_ir_solve(const cb_csr* A, const double* b, double* x, int32_t m, dou
         if (acc.restarts >= max_outer) { status = CB_ERR_NOT_CONVERGED; break; }
         launch_fill(d, 0.0, n, s);
         cb_result ir;
-        int ist = solve_impl(*A, r, d, m, inner_tol, format, &io, W, nullptr, 0, &ir, s);
+        int ist = solve_impl(*A, r, d, m, inner_tol, format, &io, W, nullptr, 0, &ir, s, nullptr, nullptr,
+                             true);
         acc.iterations += ir.iterations;
         acc.reorths += ir.reorths;
         acc.breakdowns += ir.breakdowns;

@@ -11,6 +11,8 @@
 // one coalesced run.  At most kSpmvGroups workgroups loop over the row blocks;
 // the row-to-workgroup map depends on the matrix only, keeping the norm's
 // reduction order fixed.
+#include <climits>
+
 #include "cb_internal.hpp"
 #include "epilogue.hpp"
 #include "reduce.hpp"
@@ -102,6 +104,144 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
     return nrm;
 }
 
+// Windowed form of spmv_rows for matrices whose rows reach only nearby
+// columns (a band): rows go in blocks of kWinRows; a plan (k_spmv_plan) holds
+// each block's smallest and largest column.  A block first stages its row
+// pointers and, when the block's window of x fits kWinMax doubles, that window
+// (x / d formed there once per element when DIV) in LDS with coalesced loads;
+// then each lane issues the loads of its entries for up to 8 rounds of rows at
+// once and gathers x from LDS (blocks whose window does not fit gather from
+// memory).  Scattered gathers of random columns otherwise touch a different
+// cache line per lane, and row pointer, entries and x each wait on the one
+// before, which bounds the SpMV far below the memory bandwidth.  Each row's
+// sum is formed exactly as in spmv_rows (same lanes, same order); workgroup g
+// takes the blocks g, g + G, ... so the norm's partial sums follow the block
+// order.
+constexpr int kWinRows = 256;
+constexpr int kWinMax = 3072;  // doubles of x staged per block (24 KB: four workgroups per CU)
+template <int LPR, bool DIV>
+__device__ __forceinline__ double spmv_rows_win(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const double* __restrict__ val, const double* __restrict__ xs,
+                                                double d, const double* __restrict__ b, double* __restrict__ y,
+                                                const int2* __restrict__ win, double* xw, int* rpl) {
+    constexpr int RPW = 256 / LPR;               // rows per round; kWinRows / RPW = LPR rounds per block
+    constexpr int U = LPR < 8 ? LPR : 8;         // rounds whose loads are issued together
+    const int sub = threadIdx.x / LPR;
+    const int li = threadIdx.x % LPR;
+    const int nwin = (n + kWinRows - 1) / kWinRows;
+    double nrm = 0.0;
+    for (int blk = blockIdx.x; blk < nwin; blk += gridDim.x) {
+        const int2 wr = win[blk];
+        const int lo = wr.x, span = wr.y - wr.x + 1;  // span <= 0: no entries
+        const bool staged = span > 0 && span <= kWinMax;
+        const int r0 = blk * kWinRows;
+        __syncthreads();  // the previous block's reads of the stage are done
+        // row pointers of the block's rows (rows past n: no entries)
+        rpl[threadIdx.x] = rp[min(r0 + (int)threadIdx.x, n)];
+        if (threadIdx.x == 0) rpl[kWinRows] = rp[min(r0 + kWinRows, n)];
+        if (staged) {
+            for (int i = threadIdx.x; i < span; i += 256) xw[i] = DIV ? xs[lo + i] / d : xs[lo + i];
+        }
+        __syncthreads();
+        for (int rd = 0; rd < LPR; rd += U) {
+            int lr[U], k0[U], k1[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                lr[u] = (rd + u) * RPW + sub;  // row within the block
+                k0[u] = rpl[lr[u]];
+                k1[u] = rpl[lr[u] + 1];
+            }
+            int c[U][2];
+            double v[U][2], bq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int k = k0[u] + li + e * LPR;
+                    const int kk = k < k1[u] ? k : 0;
+                    c[u][e] = ci[kk];
+                    v[u][e] = val[kk];
+                }
+                // b at the row, issued with the entries (a row past n reads row n - 1, unused)
+                bq[u] = b ? b[min(r0 + lr[u], n - 1)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double xv[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (staged) {
+                        const int off = c[u][e] - lo;  // inside the window for every real entry
+                        xv[e] = xw[min(max(off, 0), span - 1)];
+                    } else {
+                        xv[e] = DIV ? xs[c[u][e]] / d : xs[c[u][e]];
+                    }
+                }
+                double s = 0.0;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (k0[u] + li + e * LPR < k1[u]) s = fma(v[u][e], xv[e], s);
+                }
+                for (int k = k0[u] + li + 2 * LPR; k < k1[u]; k += LPR) {
+                    const int ck = ci[k];
+                    const double xk = staged ? xw[min(max(ck - lo, 0), span - 1)] : (DIV ? xs[ck] / d : xs[ck]);
+                    s = fma(val[k], xk, s);
+                }
+#pragma unroll
+                for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+                const int row = r0 + lr[u];
+                if (row < n && li == 0) {
+                    if (b) s = bq[u] - s;
+                    y[row] = s;
+                    nrm = fma(s, s, nrm);
+                }
+            }
+        }
+    }
+    return nrm;
+}
+
+// The plan of spmv_rows_win: win[blk] = (smallest, largest) column over the
+// entries of rows [kWinRows blk, kWinRows (blk + 1)) ∩ [0, n), or (0, -1) when
+// they have none.  One workgroup per block.
+__global__ __launch_bounds__(256) void k_spmv_plan(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   int2* __restrict__ win) {
+    const int blk = blockIdx.x;
+    const int r0 = blk * kWinRows, r1 = min(n, r0 + kWinRows);
+    const int k0 = rp[r0], k1 = rp[r1];
+    int lo = INT_MAX, hi = -1;
+    // the block's entries: a head up to a 16-byte boundary, then 4 at a time
+    const int ka = min(k1, (k0 + 3) & ~3);
+    for (int k = k0 + (int)threadIdx.x; k < ka; k += 256) {
+        lo = min(lo, ci[k]);
+        hi = max(hi, ci[k]);
+    }
+    for (int k = ka + 4 * (int)threadIdx.x; k < k1; k += 4 * 256) {
+        if (k + 4 <= k1) {
+            const int4 q = *reinterpret_cast<const int4*>(ci + k);
+            lo = min(min(lo, q.x), min(min(q.y, q.z), q.w));
+            hi = max(max(hi, q.x), max(max(q.y, q.z), q.w));
+        } else {
+            for (int t = k; t < k1; ++t) {
+                lo = min(lo, ci[t]);
+                hi = max(hi, ci[t]);
+            }
+        }
+    }
+    __shared__ int slo[256], shi[256];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            slo[threadIdx.x] = min(slo[threadIdx.x], slo[threadIdx.x + h]);
+            shi[threadIdx.x] = max(shi[threadIdx.x], shi[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) win[blk] = shi[0] < 0 ? make_int2(0, -1) : make_int2(slo[0], shi[0]);
+}
+
 // Short rows (at most 8 nonzeros per row on average): a wave takes 64
 // consecutive rows; their nonzeros, a contiguous run of at most 512 entries,
 // are read as 8 coalesced loads per lane, multiplied by the gathered x (x[c] /
@@ -160,14 +300,20 @@ __device__ __forceinline__ double spmv_rows_staged(int n, const int* __restrict_
 // (the same division, so the same values), ||y||^2 per workgroup.  The encode
 // runs over the 2048-row groups g = blockIdx.x, +gridDim.x, ...; the SpMV over
 // the row blocks.  w is only read, y is another buffer.
-template <int FMT>
+// WIN = 0: the staged short-row scheme (lpr 0); WIN = -1: lanes per row
+// picked at run time by lpr, no plan; WIN = LPR (8, 16, 32 or 64 lanes per
+// row): the windowed rows with the plan `win`.  Each instance holds only its
+// scheme, so the short-row kernel keeps its small register count (and its
+// occupancy: its loads wait on each other).
+template <int FMT, int WIN>
 __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __restrict__ rp,
                                                     const int* __restrict__ ci, const double* __restrict__ val,
                                                     int lpr, const double* __restrict__ w,
                                                     const double* __restrict__ divisor, double* __restrict__ y,
                                                     double* __restrict__ partials, unsigned char* __restrict__ values,
                                                     uint32_t* __restrict__ exps, int32_t* __restrict__ flag,
-                                                    const int* __restrict__ guard, int bits, int bs_log) {
+                                                    const int* __restrict__ guard, int bits, int bs_log,
+                                                    const int2* __restrict__ win) {
     if (guard && ld_ctl(guard) == 0) return;
     const double d = ld_ctl(divisor);
     const int lane = threadIdx.x & 63;
@@ -182,16 +328,23 @@ __global__ __launch_bounds__(256) void k_spmv_store(int n, int np, const int* __
     }
     if (bad) atomicOr(flag, 1);
     double nrm;
-    __shared__ double prod[4][kStagedMax];
-    switch (lpr) {
-    case 0: nrm = spmv_rows_staged<true>(n, rp, ci, val, w, d, nullptr, y, prod[threadIdx.x >> 6]); break;
-    case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    case 8: nrm = spmv_rows<8, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    case 16: nrm = spmv_rows<16, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    case 32: nrm = spmv_rows<32, true>(n, rp, ci, val, w, d, nullptr, y); break;
-    default: nrm = spmv_rows<64, true>(n, rp, ci, val, w, d, nullptr, y); break;
+    if constexpr (WIN > 0) {
+        __shared__ double xw[kWinMax];
+        __shared__ int rpl[kWinRows + 1];
+        nrm = spmv_rows_win<WIN, true>(n, rp, ci, val, w, d, nullptr, y, win, xw, rpl);
+    } else if constexpr (WIN == 0) {
+        __shared__ double prod[4][kStagedMax];
+        nrm = spmv_rows_staged<true>(n, rp, ci, val, w, d, nullptr, y, prod[threadIdx.x >> 6]);
+    } else {
+        switch (lpr) {
+        case 1: nrm = spmv_rows<1, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        case 2: nrm = spmv_rows<2, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        case 4: nrm = spmv_rows<4, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        case 8: nrm = spmv_rows<8, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        case 16: nrm = spmv_rows<16, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        case 32: nrm = spmv_rows<32, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        default: nrm = spmv_rows<64, true>(n, rp, ci, val, w, d, nullptr, y); break;
+        }
     }
     const double t = block_sum<256>(nrm);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -231,6 +384,25 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     }
 }
 
+// The same with the column-window plan (LPR 8, 16, 32 or 64).
+template <int LPR>
+__global__ __launch_bounds__(256) void k_spmv_win(int n, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ b, double* __restrict__ y,
+                                                  double* __restrict__ partials, int mode,
+                                                  const int* __restrict__ guard, const int2* __restrict__ win) {
+    if (guard && ld_ctl(guard) == 0) return;
+    __shared__ double xw[kWinMax];
+    __shared__ int rpl[kWinRows + 1];
+    const double nrm = spmv_rows_win<LPR, false>(n, rp, ci, val, x, 1.0, mode ? b : nullptr, y, win, xw, rpl);
+    if (partials) {
+        const double t = block_sum<256>(nrm);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+    }
+}
+
 // 0 selects the staged short-row scheme (at most 8 nonzeros per row on
 // average), else the lanes per row: the power of two nearest to half the
 // average row length.
@@ -251,10 +423,29 @@ int spmv_groups(int32_t n, int32_t nnz) {
     return (int)(blocks < kSpmvGroups ? blocks : kSpmvGroups);
 }
 
+int64_t spmv_plan_bytes(int32_t n) { return 8 * (((int64_t)n + kWinRows - 1) / kWinRows); }
+
+bool spmv_uses_plan(int32_t n, int32_t nnz) { return spmv_lanes_per_row(n, nnz) >= 8; }
+
+void launch_spmv_plan(const cb_csr& A, void* plan, hipStream_t s) {
+    const int nwin = (A.n + kWinRows - 1) / kWinRows;
+    k_spmv_plan<<<nwin, 256, 0, s>>>(A.n, A.row_ptr, A.col, static_cast<int2*>(plan));
+}
+
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
-                 int mode, const int* guard, hipStream_t s) {
+                 int mode, const int* guard, hipStream_t s, const void* plan) {
+    const int2* win = static_cast<const int2*>(plan);
     const int lpr = spmv_lanes_per_row(A.n, A.nnz);
     const int G = spmv_groups(A.n, A.nnz);
+    if (win && lpr >= 8) {
+        switch (lpr) {
+        case 8: k_spmv_win<8><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard, win); break;
+        case 16: k_spmv_win<16><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard, win); break;
+        case 32: k_spmv_win<32><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard, win); break;
+        default: k_spmv_win<64><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard, win); break;
+        }
+        return;
+    }
 #define CB_SPMV_CASE(L)                                                                         \
     case L:                                                                                     \
         k_spmv<L><<<G, 256, 0, s>>>(A.n, A.row_ptr, A.col, A.val, x, b, y, partials, mode, guard); \
@@ -277,16 +468,24 @@ void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, d
 
 void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, const double* w,
                        const double* divisor, double* y, double* partials, int32_t* flag, const int* guard,
-                       hipStream_t s) {
+                       hipStream_t s, const void* plan) {
+    const int2* win = static_cast<const int2*>(plan);
     const BasisView b = view_of(V);
     unsigned char* vals = static_cast<unsigned char*>(V.values) + (int64_t)col * b.col_bytes;
     uint32_t* ex = V.exps ? V.exps + (int64_t)col * b.exp_stride : nullptr;
     const int lpr = spmv_lanes_per_row(A.n, A.nnz);
     const int G = spmv_groups(A.n, A.nnz);
+#define CB_SS_LAUNCH(F, W)                                                                             \
+    k_spmv_store<F, W><<<G, 256, 0, s>>>(A.n, b.np, A.row_ptr, A.col, A.val, lpr, w, divisor, y, partials, \
+                                         vals, ex, flag, guard, b.bits, b.bs_log, win)
 #define CB_SS_CASE(F)                                                                                  \
     case F:                                                                                            \
-        k_spmv_store<F><<<G, 256, 0, s>>>(A.n, b.np, A.row_ptr, A.col, A.val, lpr, w, divisor, y,      \
-                                          partials, vals, ex, flag, guard, b.bits, b.bs_log);          \
+        if (lpr == 0) CB_SS_LAUNCH(F, 0);                                                              \
+        else if (!win || lpr < 8) CB_SS_LAUNCH(F, -1);                                                 \
+        else if (lpr == 8) CB_SS_LAUNCH(F, 8);                                                         \
+        else if (lpr == 16) CB_SS_LAUNCH(F, 16);                                                       \
+        else if (lpr == 32) CB_SS_LAUNCH(F, 32);                                                       \
+        else CB_SS_LAUNCH(F, 64);                                                                      \
         break;
     switch (kernel_format(fmt)) {
         CB_SS_CASE(CB_F64)
@@ -302,6 +501,7 @@ void launch_spmv_store(int fmt, const cb_csr& A, const cb_basis& V, int col, con
         CB_SS_CASE(CB_FRSZ2_32)
     }
 #undef CB_SS_CASE
+#undef CB_SS_LAUNCH
 }
 
 }  // namespace cb

@@ -1,7 +1,10 @@
 """GPU parity of the CSR SpMV and residual kernels against the oracle, for
 row lengths that select every scheme (the staged short-row scheme with its
 long-block fallback, and the lanes-per-row widths: empty rows, stencils,
-27-entry banded rows, long rows), plus the fused squared norm."""
+27-entry banded rows, long rows), plus the fused squared norm.  Rows of more
+than 8 entries on average run with and without the column-window plan (x
+staged in LDS per 256-row block when the block's window fits, else gathered):
+y must be bit-identical either way (each row's sum is formed the same way)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -49,11 +52,14 @@ MATRICES = {
     "long64": lambda: random_rows(700, 140.0, 2),
     "mid20": lambda: random_rows(1500, 20.0, 3),
     "skewed": lambda: skewed(3001, 4),
+    "banded50k": lambda: synth.banded_random(n=50000, half_band=1000, seed=7).A,
+    "wide20": lambda: random_rows(20000, 20.0, 6),  # windows wider than the LDS stage: gathers
 }
 
 
+@pytest.mark.parametrize("plan", [True, False])
 @pytest.mark.parametrize("name", list(MATRICES))
-def test_spmv_and_residual(name):
+def test_spmv_and_residual(name, plan):
     A = MATRICES[name]()
     rng = np.random.default_rng(5)
     x = rng.standard_normal(A.n)
@@ -61,12 +67,14 @@ def test_spmv_and_residual(name):
     Ad = cb.DeviceCSR.from_host(A.row_ptr, A.col, A.val)
     xd, bd = torch.from_numpy(x).cuda(), torch.from_numpy(b).cuda()
     n2 = torch.zeros(1, dtype=torch.float64, device="cuda")
-    y = cb.cb_spmv(Ad, xd, norm2=n2).cpu().numpy()
+    y = cb.cb_spmv(Ad, xd, norm2=n2, plan=plan).cpu().numpy()
+    y_other = cb.cb_spmv(Ad, xd, plan=not plan).cpu().numpy()
+    np.testing.assert_array_equal(y.view(np.uint64), y_other.view(np.uint64))
     y_or = oracle.spmv(A, x)
     scale = abs(A.scipy()) @ np.abs(x)
     assert np.all(np.abs(y - y_or) <= 1e-14 * scale + 1e-300)
     assert abs(n2.item() - oracle.dot(y_or, y_or)) <= 1e-13 * oracle.dot(y_or, y_or)
-    r = cb.cb_residual(Ad, bd, xd, norm2=n2).cpu().numpy()
+    r = cb.cb_residual(Ad, bd, xd, norm2=n2, plan=plan).cpu().numpy()
     r_or = b - y_or
     assert np.all(np.abs(r - r_or) <= 1e-14 * (scale + np.abs(b)))
     assert abs(n2.item() - oracle.dot(r_or, r_or)) <= 1e-13 * oracle.dot(r_or, r_or)
