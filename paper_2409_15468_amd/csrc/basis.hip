@@ -42,6 +42,10 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
 }
 
 // ----------------------------------------------------------------- load (decode)
+// Workgroup g, wave w decodes the 512-row tile starting at 2048 g + 512 w:
+// one tile per wave and many waves (a loop over several tiles per wave with
+// the next tile's loads in flight measured 6% slower: the wave then waits for
+// its own stores, where fresh waves do not).
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_load(BasisView V, int col, double* __restrict__ x) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -112,6 +116,29 @@ __global__ __launch_bounds__(kThreads) void k_project(BasisView V, int j,
 }
 
 // ----------------------------------------------------------------- CGS update / x update
+// Start of the update kernels: the guard, the device-side count jdev (if any;
+// the host's j then bounds it) and the coefficients h[0 .. j) are loaded
+// together -- one memory round trip, not three -- and the coefficients go to
+// hc in LDS (the caller synchronises before reading them).  Returns 0 if the
+// guard says the launch has nothing to do; j becomes the count to use.
+__device__ __forceinline__ int load_coefficients(const int* __restrict__ guard, const int* __restrict__ jdev,
+                                                 const double* __restrict__ h, int& j, double* hc) {
+    constexpr int HR = (kMaxRestart + 1 + kThreads - 1) / kThreads;
+    const int go = guard ? ld_ctl(guard) : 1;
+    const int jd = jdev ? ld_ctl(jdev) : j;
+    double hv[HR];
+#pragma unroll
+    for (int k = 0; k < HR; ++k) hv[k] = j > 0 ? ld_ctl(&h[min((int)threadIdx.x + kThreads * k, j - 1)]) : 0.0;
+    if (go == 0) return 0;
+    j = jd;
+#pragma unroll
+    for (int k = 0; k < HR; ++k) {
+        const int i = (int)threadIdx.x + kThreads * k;
+        if (i < j) hc[i] = hv[k];
+    }
+    return 1;
+}
+
 // w[k] += sign * sum_{c<j} h[c] * D(v_c)[k] over the row groups g, g + G, ...
 // of workgroup g; partials[g] = sum of w[k]^2 over those rows after the update
 // (row groups in order, then the waves in order), if partials != NULL, and
@@ -122,19 +149,20 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
                                                        double* __restrict__ w,
                                                        double* __restrict__ partials, int sign, int stream,
                                                        const int* __restrict__ guard, Epi e) {
-    if (guard && ld_ctl(guard) == 0) return;
-    if (jdev) j = ld_ctl(jdev);
     __shared__ double elds[kEpiLds];
     // the coefficients (written by an earlier kernel), read once into LDS
     __shared__ double hc[kMaxRestart + 1];
     __shared__ double stage[kThreads / 64][kTile];
-    for (int i = threadIdx.x; i < j; i += kThreads) hc[i] = ld_ctl(&h[i]);
+    const int go = load_coefficients(guard, jdev, h, j, hc);
+    if (!go) return;
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ngroups = row_groups_dev(V.np);
     double nrm = 0.0;
     for (int rg = blockIdx.x; rg < ngroups; rg += gridDim.x) {
         const int tile0 = rg * kRowsPerWG + wave * kTile;
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);  // in flight with the basis loads
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -146,8 +174,6 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
             if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
             else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
         }
-        double wv[8];
-        load_rows<FMT>(w, tile0, lane, V.n, wv);
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -171,26 +197,30 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
 // ||w||^2 at c = j; the epilogue (FUSED_CHECK) keeps u only if step 7 asks for
 // the second pass.  Sums are formed in the same orders as k_subtract (norm)
 // and k_project with one column chunk (u).
+// At most 256 registers (two waves per SIMD): with one, a launch of more
+// workgroups than CUs runs in two rounds and pays its start-up twice.
 template <int FMT, int U>
-__global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int j,
+__global__ __launch_bounds__(kThreads, 2) void k_subtract_project(BasisView V, int j,
                                                                const double* __restrict__ h,
                                                                double* __restrict__ w,
                                                                double* __restrict__ partials, int stream,
                                                                const int* __restrict__ guard, Epi e) {
-    if (guard && ld_ctl(guard) == 0) return;
     __shared__ double elds[kEpiLds];
     __shared__ double hc[kMaxRestart + 1];
     __shared__ double red[kThreads / 64][kMaxRestart + 2];
     __shared__ double stage[kThreads / 64][kTile];
+    const int go = load_coefficients(guard, nullptr, h, j, hc);
+    if (!go) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int G = gridDim.x;
     const int ngroups = row_groups_dev(V.np);
-    for (int i = tid; i < j; i += kThreads) hc[i] = ld_ctl(&h[i]);
     for (int i = lane; i < j; i += 64) red[wave][i] = 0.0;
     __syncthreads();
     double nrm = 0.0;
     for (int rg = blockIdx.x; rg < ngroups; rg += G) {
         const int tile0 = rg * kRowsPerWG + wave * kTile;
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);  // in flight with the basis loads
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -199,8 +229,6 @@ __global__ __launch_bounds__(kThreads) void k_subtract_project(BasisView V, int 
         // projection below re-reads these columns, last first, right away
         if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
         else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
-        double wv[8];
-        load_rows<FMT>(w, tile0, lane, V.n, wv);
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {

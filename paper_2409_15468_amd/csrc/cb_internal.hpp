@@ -139,6 +139,7 @@ inline BasisView view_of(const cb_basis& V) {
 
 // SpMV geometry: lanes per row and rows per workgroup depend on the matrix only.
 constexpr int kSpmvGroups = 2048;
+constexpr int kXcds = 8;  // accelerator dies (XCDs), each with its own L2; workgroup w runs on XCD w % 8
 int spmv_lanes_per_row(int32_t n, int32_t nnz);
 int spmv_groups(int32_t n, int32_t nnz);
 int64_t reduce_workspace_bytes(int32_t n, int32_t ncols, int32_t nnz);

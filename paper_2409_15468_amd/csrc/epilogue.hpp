@@ -147,22 +147,61 @@ __device__ __forceinline__ Snap snapshot(const Epi& e) {
     return z;
 }
 
+// What the last workgroup's step logic reads that no workgroup of the launch
+// writes: the SpMV's ||A v||^2 partials (the first batch of sum_partials: each
+// thread's loads at t, t + 256, ...), H column j, the earlier rotations and the
+// control block.  The last workgroup issues all of these loads together with
+// those of its final column sums, so they cost one memory round trip instead
+// of one each.  Loads use clamped indices (no branches); values past the end
+// are masked where they are used.
+constexpr int kPreOm = 8;
+constexpr int kPreRows = (kMaxRestart + 255) / 256;  // rows of H column j per thread
+struct Pre {
+    double om[kPreOm];
+    double h[kPreRows], c[kPreRows], s[kPreRows], u[kPreRows];
+    Snap z;
+};
+__device__ __forceinline__ void prefetch(const Epi& e, Pre& p) {
+    if (e.mode == EPI_STORE) return;
+    const int t = threadIdx.x, j = e.j;
+    if (e.mode == EPI_STEP_CHECK || e.mode == EPI_FUSED_CHECK) {
+#pragma unroll
+        for (int u = 0; u < kPreOm; ++u) p.om[u] = ld_ctl(e.extra + min(t + 256 * u, e.extra_G - 1));
+    }
+    const double* h = e.H + (int64_t)j * (e.m + 1);
+    const int jc = max(j - 1, 0);
+#pragma unroll
+    for (int k = 0; k < kPreRows; ++k) {
+        const int i = t + 256 * k;
+        p.h[k] = h[min(i, j)];
+        p.c[k] = e.cs[min(i, jc)];
+        p.s[k] = e.sn[min(i, jc)];
+        p.u[k] = 0.0;
+    }
+    p.z = snapshot(e);
+}
+
 // Fig. 1 steps 12-17 for column j once h_{1:j+1,j} is final: breakdown test,
 // Givens rotations, implicit residual, end-of-cycle decision.  Called by all
 // threads of one workgroup; H column j, cs and sn are staged in LDS; z is
 // valid in thread 0.  Results go to memory with plain stores (read by later
 // kernels on the stream and by the host after it synchronises).
-__device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, const Snap& z, double* lds) {
+__device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double hn, const Snap& z, double* lds,
+                                            const Pre& p) {
     State& s = *e.st;
     const int j = e.j;
     double* h = e.H + (int64_t)j * (e.m + 1);
     double* lh = lds;                // j + 2 entries
     double* lc = lds + (j + 2);      // j entries
     double* ls = lc + j;             // j entries
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) lh[i] = h[i];
-    for (int i = threadIdx.x; i < j; i += blockDim.x) {
-        lc[i] = e.cs[i];
-        ls[i] = e.sn[i];
+#pragma unroll
+    for (int k = 0; k < kPreRows; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i <= j) lh[i] = p.h[k];
+        if (i < j) {
+            lc[i] = p.c[k];
+            ls[i] = p.s[k];
+        }
     }
     __syncthreads();
     if (!isfinite(hn)) {
@@ -177,20 +216,21 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
         if (hn == 0.0) breakdown = 1;
         lh[j + 1] = hn;
         // the earlier rotations in order; the entry carried from rotation i to
-        // i+1 stays in a register, and the LDS reads of each chunk of 16
-        // rotations are issued together ahead of the arithmetic
+        // i+1 stays in a register, and the LDS reads of each chunk of 8
+        // rotations are issued together ahead of the arithmetic (chunks of 8
+        // keep this thread's registers below the kernels' main loops)
         double carry = lh[0];
-        for (int i0 = 0; i0 < j; i0 += 16) {
-            double b[16], c[16], sn[16];
+        for (int i0 = 0; i0 < j; i0 += 8) {
+            double b[8], c[8], sn[8];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 const int i = min(i0 + k, j - 1);
                 b[k] = lh[i + 1];
                 c[k] = lc[i];
                 sn[k] = ls[i];
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 if (i0 + k < j) {
                     lh[i0 + k] = c[k] * carry + sn[k] * b[k];
                     carry = -sn[k] * carry + c[k] * b[k];
@@ -297,18 +337,28 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 
 // Fig. 1 steps 6-12 once ||w||^2 = t after a Gram-Schmidt pass is known
 // (the STEP_CHECK / FUSED_CHECK / REORTH_FINISH modes; last workgroup, all
-// threads): h_{j+1,j}, the step 7 test, the breakdown test, then the Givens
-// update of finish_step when the step is complete.  In FUSED_CHECK mode u
-// (e.out) is added to H column j when the second pass is needed, else dropped.
-__device__ __forceinline__ void step_logic(const Epi& e, double t, double* lds) {
-    // the SpMV's ||A v||^2 partials, when this step needs omega
+// threads, p from prefetch): h_{j+1,j}, the step 7 test, the breakdown test,
+// then the Givens update of finish_step when the step is complete.  In
+// FUSED_CHECK mode u (p.u, also in e.out) is added to H column j when the
+// second pass is needed, else dropped.
+__device__ __forceinline__ void step_logic(const Epi& e, double t, double* lds, const Pre& p) {
+    // the SpMV's ||A v||^2 partials, when this step needs omega: the sums of
+    // sum_partials, from the prefetched first batch when that is all of them
     double om2 = 0.0;
-    if (e.mode != EPI_REORTH_FINISH) om2 = sum_partials(e.extra, e.extra_G);
+    if (e.mode != EPI_REORTH_FINISH) {
+        if (e.extra_G <= kPreOm * 256) {
+            double a = 0.0;
+#pragma unroll
+            for (int u = 0; u < kPreOm; ++u) a += (int)threadIdx.x + 256 * u < e.extra_G ? p.om[u] : 0.0;
+            om2 = block_sum<256>(a);
+        } else {
+            om2 = sum_partials(e.extra, e.extra_G);
+        }
+    }
     __shared__ int do_finish, bd, keep_u;
     __shared__ double hn_s;
-    Snap z;
+    const Snap& z = p.z;
     if (threadIdx.x == 0) {
-        z = snapshot(e);
         State& s = *e.st;
         do_finish = 0;
         bd = 0;
@@ -344,39 +394,57 @@ __device__ __forceinline__ void step_logic(const Epi& e, double t, double* lds) 
     __syncthreads();
     if (keep_u) {  // h_{1:j+1,j} += u
         double* h = e.H + (int64_t)e.j * (e.m + 1);
-        for (int i = threadIdx.x; i < e.ncols - 1; i += blockDim.x) h[i] += e.out[i];
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPreRows; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            if (i < e.ncols - 1) h[i] = p.h[k] + p.u[k];
+        }
     }
-    if (do_finish) finish_step(e, bd, hn_s, z, lds);
+    if (do_finish) finish_step(e, bd, hn_s, z, lds, p);
 }
 
 // Run by every workgroup of the launch after its partials are written
 // (all threads; blockDim.x == 256).
 __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double* lds) {
     if (!reduce_tickets(e, partials, lds)) return;
+    Pre p;
+    prefetch(e, p);  // in flight with the final sums' loads
     if (e.mode == EPI_FUSED_CHECK) {
-        // u_c (c < ncols - 1) into e.out, ||w||^2 from the last column
+        // u_c (c < ncols - 1) into e.out and p.u, ||w||^2 from the last column
         __shared__ double nn;
-        for (int c0 = 0; c0 < e.ncols; c0 += 256) {
+#pragma unroll
+        for (int k = 0; k <= kPreRows; ++k) {
+            const int c0 = 256 * k;
+            if (c0 >= e.ncols) break;
             const int nc = min(256, e.ncols - c0);
             reduce_final(e, partials, c0, nc, lds);
-            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-                if (c0 + i < e.ncols - 1) e.out[c0 + i] = lds[i];
-                else nn = lds[i];
+            const int i = threadIdx.x;
+            if (i < nc) {
+                if (c0 + i < e.ncols - 1) {
+                    e.out[c0 + i] = lds[i];
+                    if (k < kPreRows) p.u[k] = lds[i];
+                } else {
+                    nn = lds[i];
+                }
             }
             __syncthreads();
         }
-        step_logic(e, nn, lds);
+        step_logic(e, nn, lds, p);
         return;
     }
     if ((e.mode == EPI_STORE && e.ncols > 1) || e.mode == EPI_REORTH_PROJECT) {
-        for (int c0 = 0; c0 < e.ncols; c0 += 256) {
+        double* h = e.H + (int64_t)e.j * (e.m + 1);
+#pragma unroll
+        for (int k = 0; k <= kPreRows; ++k) {
+            const int c0 = 256 * k;
+            if (c0 >= e.ncols) break;
             const int nc = min(256, e.ncols - c0);
             reduce_final(e, partials, c0, nc, lds);
-            for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+            const int i = threadIdx.x;
+            if (i < nc) {
                 const double u = lds[i];
                 e.out[c0 + i] = u;
-                if (e.mode == EPI_REORTH_PROJECT) e.H[(int64_t)e.j * (e.m + 1) + c0 + i] += u;
+                if (e.mode == EPI_REORTH_PROJECT && k < kPreRows) h[c0 + i] = p.h[k] + u;
             }
             __syncthreads();
         }
@@ -389,7 +457,7 @@ __device__ __forceinline__ void epilogue(const Epi& e, double* partials, double*
         if (threadIdx.x == 0) e.out[0] = t;
         return;
     }
-    step_logic(e, t, lds);
+    step_logic(e, t, lds, p);
 }
 
 }  // namespace dev

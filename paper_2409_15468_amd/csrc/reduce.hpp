@@ -58,6 +58,30 @@ __device__ __forceinline__ void swap16(double& a, double& b) {
     b = __hiloint2double(hi[1], lo[1]);
 }
 
+// Sum over each aligned group of L lanes (L = 1, 2, 4, ..., 64), returned in
+// every lane of the group: the neighbour / pair / half-row-mirror / row-mirror
+// DPP butterfly of wave_sum inside 16-lane rows, then 16- and 32-lane swaps
+// (a + b after swapping a copy of v with itself leaves the pair's sum in both
+// lanes).  All VALU moves; the order is fixed.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+    if constexpr (L >= 2) v += dpp_f64<0xB1>(v);
+    if constexpr (L >= 4) v += dpp_f64<0x4E>(v);
+    if constexpr (L >= 8) v += dpp_f64<0x141>(v);
+    if constexpr (L >= 16) v += dpp_f64<0x140>(v);
+    if constexpr (L >= 32) {
+        double a = v, b = v;
+        swap16(a, b);
+        v = a + b;
+    }
+    if constexpr (L >= 64) {
+        double a = v, b = v;
+        swap32(a, b);
+        v = a + b;
+    }
+    return v;
+}
+
 // Eight wave sums at once (a transposed reduce-scatter): on return lane 8c
 // (c = 0..7) holds sum over the 64 lanes of p[c].  Halves of the wave trade
 // half their columns (32-lane swap), then rows (16-lane swap), then half-rows

@@ -5,12 +5,12 @@
 // rows' nonzeros in LDS from coalesced loads and each lane adds its row's
 // products in CSR order (spmv_rows_staged).  Longer rows: a group of LPR lanes
 // works on one row: lane i of the group accumulates the row's entries i,
-// i+LPR, ... with FMA in CSR order, then the group sums with a fixed shuffle
-// tree; LPR is the power of two nearest to half the average row length, so
-// most lanes own one or two nonzeros and a row's column indices are read as
-// one coalesced run.  At most kSpmvGroups workgroups loop over the row blocks;
-// the row-to-workgroup map depends on the matrix only, keeping the norm's
-// reduction order fixed.
+// i+LPR, ... with FMA in CSR order, then the group sums with a fixed tree of
+// cross-lane moves (group_sum: DPP inside 16-lane rows); LPR is the power of
+// two nearest to half the average row length, so most lanes own one or two
+// nonzeros and a row's column indices are read as one coalesced run.  At most
+// kSpmvGroups workgroups loop over the row blocks; the row-to-workgroup map
+// depends on the matrix only, keeping the norm's reduction order fixed.
 #include <climits>
 
 #include "cb_internal.hpp"
@@ -22,12 +22,31 @@ namespace cb {
 
 using namespace dev;
 
-// y = A x over the row blocks blk = blockIdx.x, +gridDim.x, ... of 256/LPR rows
+// The row blocks of this workgroup, XCD-aware.  Workgroups are dispatched to
+// the XCDs round-robin (w -> XCD w % kXcds) and each XCD has its own L2, so
+// when the grid is a multiple of kXcds the nblk blocks are cut into kXcds
+// contiguous ranges, one per XCD, whose workgroups take the blocks of the
+// range in turn: workgroups of one XCD then work on neighbouring rows at the
+// same time and share in its L2 the parts of x those rows read.  Otherwise
+// workgroup w takes the blocks w, w + G, ....  Blocks first, first + stride,
+// ... below end; the map depends on (nblk, G) only.
+struct BlockSeq {
+    int first, stride, end;
+};
+__device__ __forceinline__ BlockSeq xcd_blocks(int nblk) {
+    const int G = gridDim.x, w = blockIdx.x;
+    if (G % kXcds != 0) return {w, G, nblk};
+    const int x = w % kXcds;
+    const int lo = (int)((int64_t)nblk * x / kXcds), hi = (int)((int64_t)nblk * (x + 1) / kXcds);
+    return {lo + w / kXcds, G / kXcds, hi};
+}
+
+// y = A x over the row blocks of 256/LPR rows given by xcd_blocks
 // (x[c] read as xs[c] / d when DIV: the normalised vector formed on the fly);
 // with b != NULL the result is b - A x.  Returns this thread's share of
 // ||y||^2.  Lane li of a row's group of LPR lanes accumulates the row's
-// entries li, li + LPR, ... with FMA in CSR order, then the group sums with a
-// fixed shuffle tree.  The loads are what limits a row: row pointer, then
+// entries li, li + LPR, ... with FMA in CSR order, then the group sums with
+// group_sum.  The loads are what limits a row: row pointer, then
 // column index and value, then the x gather, each waiting on the one before.
 // So each group works on U row blocks at once and issues the loads of every
 // level for all U rows (the first two entries per lane, unconditionally, with
@@ -41,10 +60,10 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
     const int nblk = (n + RPW - 1) / RPW;
-    const int G = gridDim.x;
+    const BlockSeq bs = xcd_blocks(nblk);
     double nrm = 0.0;
     if (__builtin_amdgcn_readfirstlane(rp[n]) == 0) {  // no entries at all: y = b or 0
-        for (int blk = blockIdx.x; blk < nblk; blk += G) {
+        for (int blk = bs.first; blk < bs.end; blk += bs.stride) {
             const int row = blk * RPW + sub;
             if (row < n && li == 0) {
                 const double t = b ? b[row] : 0.0;
@@ -54,11 +73,13 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
         }
         return nrm;
     }
-    for (int blk0 = blockIdx.x; blk0 < nblk; blk0 += U * G) {
+    for (int blk0 = bs.first; blk0 < bs.end; blk0 += U * bs.stride) {
         int row[U], k0[U], k1[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            row[u] = (blk0 + u * G) * RPW + sub;  // rows >= n have no entries
+            // rows >= n (and blocks past this workgroup's share) have no entries
+            const int blk = blk0 + u * bs.stride;
+            row[u] = blk < bs.end ? blk * RPW + sub : n;
             const int r = min(row[u], n);
             k0[u] = rp[r];
             k1[u] = rp[min(row[u] + 1, n)];
@@ -92,8 +113,7 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
                 const double xk = DIV ? xs[ci[k]] / d : xs[ci[k]];
                 s = fma(val[k], xk, s);
             }
-#pragma unroll
-            for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
+            s = group_sum<LPR>(s);
             if (row[u] < n && li == 0) {
                 if (b) s = b[row[u]] - s;
                 y[row[u]] = s;
@@ -114,89 +134,110 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
 // memory).  Scattered gathers of random columns otherwise touch a different
 // cache line per lane, and row pointer, entries and x each wait on the one
 // before, which bounds the SpMV far below the memory bandwidth.  Each row's
-// sum is formed exactly as in spmv_rows (same lanes, same order); workgroup g
-// takes the blocks g, g + G, ... so the norm's partial sums follow the block
-// order.
+// sum is formed exactly as in spmv_rows (same lanes, same order); the blocks
+// go to workgroups by xcd_blocks, a map fixed by the block count and the grid,
+// so the norm's partial sums do not depend on timing.
 constexpr int kWinRows = 256;
 constexpr int kWinMax = 3072;  // doubles of x staged per block (24 KB: four workgroups per CU)
+// The rows of one block of spmv_rows_win once its row pointers (and, STAGED,
+// its window of x) sit in LDS.  STAGED is a template argument so that the
+// gathers from LDS and those from memory are separate code: mixed in one loop
+// the compiler's merged control flow lets a global load and an LDS read share
+// a destination register, and every LDS read then waits for all entry loads.
+template <int LPR, bool DIV, bool STAGED>
+__device__ __forceinline__ void spmv_win_block(int n, int r0, const int* __restrict__ ci,
+                                               const double* __restrict__ val, const double* __restrict__ xs,
+                                               double d, const double* __restrict__ b, double* __restrict__ y,
+                                               const double* xw, const int* rpl, int lo, int span, double& nrm) {
+    constexpr int RPW = 256 / LPR;               // rows per round; kWinRows / RPW = LPR rounds per block
+    constexpr int U = LPR < 8 ? LPR : 8;         // rounds whose loads are issued together
+    const int sub = threadIdx.x / LPR;
+    const int li = threadIdx.x % LPR;
+    auto gather = [&](int col) -> double {
+        if (STAGED) return xw[min(max(col - lo, 0), span - 1)];  // inside the window for every real entry
+        return DIV ? xs[col] / d : xs[col];
+    };
+    for (int rd = 0; rd < LPR; rd += U) {
+        int lr[U], k0[U], k1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            lr[u] = (rd + u) * RPW + sub;  // row within the block
+            k0[u] = rpl[lr[u]];
+            k1[u] = rpl[lr[u] + 1];
+        }
+        int c[U][2];
+        double v[U][2], bq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = k0[u] + li + e * LPR;
+                const int kk = k < k1[u] ? k : 0;
+                c[u][e] = ci[kk];
+                v[u][e] = val[kk];
+            }
+            // b at the row, issued with the entries (a row past n reads row n - 1, unused)
+            bq[u] = b ? b[min(r0 + lr[u], n - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double xv[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) xv[e] = gather(c[u][e]);
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (k0[u] + li + e * LPR < k1[u]) s = fma(v[u][e], xv[e], s);
+            }
+            for (int k = k0[u] + li + 2 * LPR; k < k1[u]; k += LPR) s = fma(val[k], gather(ci[k]), s);
+            s = group_sum<LPR>(s);
+            const int row = r0 + lr[u];
+            if (row < n && li == 0) {
+                if (b) s = bq[u] - s;
+                y[row] = s;
+                nrm = fma(s, s, nrm);
+            }
+        }
+    }
+}
+
 template <int LPR, bool DIV>
 __device__ __forceinline__ double spmv_rows_win(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ val, const double* __restrict__ xs,
                                                 double d, const double* __restrict__ b, double* __restrict__ y,
                                                 const int2* __restrict__ win, double* xw, int* rpl) {
-    constexpr int RPW = 256 / LPR;               // rows per round; kWinRows / RPW = LPR rounds per block
-    constexpr int U = LPR < 8 ? LPR : 8;         // rounds whose loads are issued together
-    const int sub = threadIdx.x / LPR;
-    const int li = threadIdx.x % LPR;
     const int nwin = (n + kWinRows - 1) / kWinRows;
+    const BlockSeq bs = xcd_blocks(nwin);
     double nrm = 0.0;
-    for (int blk = blockIdx.x; blk < nwin; blk += gridDim.x) {
+    for (int blk = bs.first; blk < bs.end; blk += bs.stride) {
         const int2 wr = win[blk];
         const int lo = wr.x, span = wr.y - wr.x + 1;  // span <= 0: no entries
         const bool staged = span > 0 && span <= kWinMax;
         const int r0 = blk * kWinRows;
         __syncthreads();  // the previous block's reads of the stage are done
-        // row pointers of the block's rows (rows past n: no entries)
-        rpl[threadIdx.x] = rp[min(r0 + (int)threadIdx.x, n)];
-        if (threadIdx.x == 0) rpl[kWinRows] = rp[min(r0 + kWinRows, n)];
+        // row pointers of the block's rows (rows past n: no entries) and the
+        // window of x, 12 elements per thread at most (kWinMax / 256), all
+        // loads issued before any is used
+        const int rpa = rp[min(r0 + (int)threadIdx.x, n)];
+        const int rpb = rp[min(r0 + kWinRows, n)];
         if (staged) {
-            for (int i = threadIdx.x; i < span; i += 256) xw[i] = DIV ? xs[lo + i] / d : xs[lo + i];
+            constexpr int E = kWinMax / 256;
+            double t[E];
+#pragma unroll
+            for (int u = 0; u < E; ++u) t[u] = xs[lo + min((int)threadIdx.x + 256 * u, span - 1)];
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int i = (int)threadIdx.x + 256 * u;
+                if (i < span) xw[i] = DIV ? t[u] / d : t[u];
+            }
         }
+        rpl[threadIdx.x] = rpa;
+        if (threadIdx.x == 0) rpl[kWinRows] = rpb;
         __syncthreads();
-        for (int rd = 0; rd < LPR; rd += U) {
-            int lr[U], k0[U], k1[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                lr[u] = (rd + u) * RPW + sub;  // row within the block
-                k0[u] = rpl[lr[u]];
-                k1[u] = rpl[lr[u] + 1];
-            }
-            int c[U][2];
-            double v[U][2], bq[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int k = k0[u] + li + e * LPR;
-                    const int kk = k < k1[u] ? k : 0;
-                    c[u][e] = ci[kk];
-                    v[u][e] = val[kk];
-                }
-                // b at the row, issued with the entries (a row past n reads row n - 1, unused)
-                bq[u] = b ? b[min(r0 + lr[u], n - 1)] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                double xv[2];
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    if (staged) {
-                        const int off = c[u][e] - lo;  // inside the window for every real entry
-                        xv[e] = xw[min(max(off, 0), span - 1)];
-                    } else {
-                        xv[e] = DIV ? xs[c[u][e]] / d : xs[c[u][e]];
-                    }
-                }
-                double s = 0.0;
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    if (k0[u] + li + e * LPR < k1[u]) s = fma(v[u][e], xv[e], s);
-                }
-                for (int k = k0[u] + li + 2 * LPR; k < k1[u]; k += LPR) {
-                    const int ck = ci[k];
-                    const double xk = staged ? xw[min(max(ck - lo, 0), span - 1)] : (DIV ? xs[ck] / d : xs[ck]);
-                    s = fma(val[k], xk, s);
-                }
-#pragma unroll
-                for (int off = LPR / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, LPR);
-                const int row = r0 + lr[u];
-                if (row < n && li == 0) {
-                    if (b) s = bq[u] - s;
-                    y[row] = s;
-                    nrm = fma(s, s, nrm);
-                }
-            }
-        }
+        if (staged)
+            spmv_win_block<LPR, DIV, true>(n, r0, ci, val, xs, d, b, y, xw, rpl, lo, span, nrm);
+        else
+            spmv_win_block<LPR, DIV, false>(n, r0, ci, val, xs, d, b, y, xw, rpl, lo, span, nrm);
     }
     return nrm;
 }
@@ -248,45 +289,69 @@ __global__ __launch_bounds__(256) void k_spmv_plan(int n, const int* __restrict_
 // d when DIV) into LDS, and each lane then adds its row's products in CSR
 // order.  A run longer than 512 entries falls back to one lane per row.
 // With b != NULL the result is b - A x.  Returns this thread's share of
-// ||y||^2.
+// ||y||^2.  The latency chain of a block is row pointers -> column indices
+// and values -> x: the 8 loads of each level are issued together
+// (unconditionally, entries past the run read its last entry again and are
+// dropped), and the next block's row pointers are loaded while this block
+// runs, so a block waits on two memory round trips, not sixteen.
 constexpr int kStagedMax = 512;
 template <bool DIV>
 __device__ __forceinline__ double spmv_rows_staged(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const double* __restrict__ val, const double* __restrict__ xs,
                                                    double d, const double* __restrict__ b, double* __restrict__ y,
                                                    double* prod) {
+    constexpr int C = kStagedMax / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwb = (n + 63) / 64;  // blocks of 64 rows
+    const int nwb = (n + 63) / 64;  // blocks of 64 rows, 4 per workgroup block
+    const BlockSeq bs = xcd_blocks((nwb + 3) / 4);
+    // the lane's row pointers in workgroup block gb (rows past n: no entries)
+    auto ptrs = [&](int gb, int& a, int& e) {
+        const int r = min(gb * 4 + wave, nwb - 1) * 64 + lane;
+        a = rp[min(r, n)];
+        e = rp[min(r + 1, n)];
+    };
     double nrm = 0.0;
-    for (int wb = blockIdx.x * 4 + wave; wb < nwb; wb += gridDim.x * 4) {
+    int my0 = 0, my1 = 0;
+    if (bs.first < bs.end) ptrs(bs.first, my0, my1);
+    for (int gb = bs.first; gb < bs.end; gb += bs.stride) {
+        const int wb = gb * 4 + wave;
+        if (wb >= nwb) break;  // the last workgroup block's missing waves
         const int r = wb * 64 + lane;
-        const int rr = r < n ? r : n;
-        const int my0 = rp[rr], my1 = r < n ? rp[r + 1] : my0;
-        const int k0 = __builtin_amdgcn_readfirstlane(my0);
-        const int k1 = __builtin_amdgcn_readlane(my1, 63);
+        const int c0 = my0, c1 = my1;
+        if (gb + bs.stride < bs.end) ptrs(gb + bs.stride, my0, my1);  // the next block's, in flight
+        const int k0 = __builtin_amdgcn_readfirstlane(c0);
+        const int k1 = __builtin_amdgcn_readlane(c1, 63);
+        const double bv = b ? b[min(r, n - 1)] : 0.0;
         double s = 0.0;
         if (k1 - k0 <= kStagedMax) {
+            if (k1 > k0) {
+                int cc[C];
+                double vv[C], xv[C];
 #pragma unroll
-            for (int c = 0; c < kStagedMax / 64; ++c) {
-                const int k = k0 + c * 64 + lane;
-                double pv = 0.0;
-                if (k < k1) {
-                    const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
-                    pv = val[k] * xv;
+                for (int c = 0; c < C; ++c) {
+                    const int k = min(k0 + c * 64 + lane, k1 - 1);
+                    cc[c] = ci[k];
+                    vv[c] = val[k];
                 }
-                prod[c * 64 + lane] = pv;
+#pragma unroll
+                for (int c = 0; c < C; ++c) xv[c] = xs[cc[c]];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const bool live = k0 + c * 64 + lane < k1;
+                    prod[c * 64 + lane] = live ? vv[c] * (DIV ? xv[c] / d : xv[c]) : 0.0;
+                }
             }
             __builtin_amdgcn_wave_barrier();
-            for (int k = my0; k < my1; ++k) s += prod[k - k0];
+            for (int k = c0; k < c1; ++k) s += prod[k - k0];
             __builtin_amdgcn_wave_barrier();
         } else {
-            for (int k = my0; k < my1; ++k) {
-                const double xv = DIV ? xs[ci[k]] / d : xs[ci[k]];
-                s = fma(val[k], xv, s);
+            for (int k = c0; k < c1; ++k) {
+                const double xk = DIV ? xs[ci[k]] / d : xs[ci[k]];
+                s = fma(val[k], xk, s);
             }
         }
         if (r < n) {
-            if (b) s = b[r] - s;
+            if (b) s = bv - s;
             y[r] = s;
             nrm = fma(s, s, nrm);
         }
@@ -376,7 +441,7 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
                                               double* __restrict__ partials, int mode,
                                               const int* __restrict__ guard) {
     if (guard && ld_ctl(guard) == 0) return;
-    // row blocks blockIdx.x, blockIdx.x + gridDim.x, ... (the grid depends on n only)
+    // row blocks by xcd_blocks (the grid depends on the matrix only)
     const double nrm = spmv_rows<LPR, false>(n, rp, ci, val, x, 1.0, mode ? b : nullptr, y);
     if (partials) {
         const double t = block_sum<256>(nrm);
