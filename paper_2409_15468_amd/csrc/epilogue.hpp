@@ -59,6 +59,9 @@ enum EpiMode : int {
                             // step 7 test; u kept (h += u) only if it asks for it
 };
 
+// Arnoldi steps between the progress reports of a cycle (Epi::prog).
+constexpr int kProgressEvery = 4;
+
 struct Epi {
     int mode;
     int ncols;             // sums to form
@@ -79,6 +82,7 @@ struct Epi {
     int m;
     double col_bytes;
     int fused;             // this cycle runs the first update fused with the second projection
+    int* prog;             // NULL, or host-mapped words: [0] steps finished in the cycle, [1] 1 once it ended
 };
 
 namespace dev {
@@ -209,6 +213,7 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
             s.active = 0;
             s.stop = 1;
             s.status = CB_ERR_NONFINITE;
+            if (e.prog) __hip_atomic_store(&e.prog[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         return;
     }
@@ -253,9 +258,18 @@ __device__ __forceinline__ void finish_step(const Epi& e, int breakdown, double 
         s.steps = j + 1;
         s.gabs = gabs;
         e.hist[j] = gabs;
-        if (gabs <= z.tol_abs || breakdown || iters >= z.max_iters || j + 1 == e.m) {
+        const bool ended = gabs <= z.tol_abs || breakdown || iters >= z.max_iters || j + 1 == e.m;
+        if (ended) {
             s.active = 0;
             s.breakdowns = z.breakdowns + breakdown;
+        }
+        // the host paces its launches by these (they order nothing on the
+        // GPU); every kProgressEvery steps and at the end only, since the
+        // launch cannot complete before its write to host memory has
+        if (e.prog) {
+            if (ended) __hip_atomic_store(&e.prog[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ended || (j + 1) % kProgressEvery == 0)
+                __hip_atomic_store(&e.prog[0], j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
     __syncthreads();

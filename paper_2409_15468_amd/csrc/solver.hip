@@ -21,6 +21,7 @@
 // waits once per cycle, after the explicit residual of the restart (step 1 /
 // 18, Eq. 4) has been evaluated, to learn whether to stop.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -223,6 +224,61 @@ struct Pinned {
 };
 static thread_local Pinned g_pinned;
 
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Two words of pinned, mapped, coherent host memory per host thread through
+// which the solver's last workgroup reports a cycle's progress (steps finished,
+// cycle ended) while the cycle runs.  NULL device pointer if unavailable.
+struct Progress {
+    int32_t* h = nullptr;
+    int32_t* d = nullptr;
+    bool tried = false;
+    bool get() {
+        if (!tried) {
+            tried = true;
+            void* p = nullptr;
+            void* dp = nullptr;
+            if (hipHostMalloc(&p, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return false;
+            if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) {
+                (void)hipHostFree(p);
+                return false;
+            }
+            h = static_cast<int32_t*>(p);
+            d = static_cast<int32_t*>(dp);
+        }
+        return h != nullptr;
+    }
+};
+static thread_local Progress g_progress;
+
+// Launches are enqueued at most this many Arnoldi steps ahead of what the GPU
+// has reported finished (reports come every kProgressEvery steps, so the host
+// runs 4-8 steps ahead).  Steps after the cycle's last are launches that only
+// read their guard and return (~2.4 us of GPU time each, four per step);
+// enqueuing a cycle's m steps at once spent that on every step past
+// convergence.
+constexpr int kStepsAhead = 8;
+
+// Wait until the GPU has finished `target` steps of the current cycle or ended
+// it (spinning on the host-mapped words); returns true if the cycle has ended.
+// The wait also ends when the stream has drained (no launch left that could
+// report) or after 10 s, after which the caller simply enqueues the remaining
+// steps: every step's launches check the cycle's guard on the GPU, so pacing
+// affects only how many of them run, never the result.
+static bool wait_progress(const volatile int32_t* p, int target, hipStream_t s) {
+    const double t0 = now_s();
+    for (unsigned it = 0;; ++it) {
+        if (p[1]) return true;
+        if (p[0] >= target) return false;
+        if ((it & 4095u) == 4095u) {
+            if (hipStreamQuery(s) != hipErrorNotReady) return p[1] != 0;
+            if (now_s() - t0 > 10.0) return false;
+        }
+    }
+}
+
 struct Ws {
     unsigned char* base;
     Layout L;
@@ -230,9 +286,6 @@ struct Ws {
     T* at(int64_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
-static double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 // ||x||^2 of a device vector into *dst (device), using the partial buffer.
 static void enqueue_sumsq(const double* x, int n, double* part, double* dst, hipStream_t s) {
@@ -304,6 +357,11 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
     step_e.hist = hist;
     step_e.m = m;
     step_e.col_bytes = cbytes;
+    int32_t* prog_h = nullptr;
+    if (g_progress.get()) {
+        prog_h = g_progress.h;
+        step_e.prog = g_progress.d;
+    }
 
     State* hs = static_cast<State*>(g_pinned.get(sizeof(State) + (size_t)m * 8));
     if (!hs) return fail(CB_ERR_HIP, "hipHostMalloc failed");
@@ -352,6 +410,11 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
             step_e.fused = fused;
             double* wc = w;   // the current w (the residual r first)
             double* wn = w2;  // the buffer the next SpMV writes
+            if (prog_h) {     // the stream is idle here (synchronised above)
+                prog_h[0] = 0;
+                prog_h[1] = 0;
+                std::atomic_thread_fence(std::memory_order_seq_cst);
+            }
             for (int j = 0; j < m; ++j) {
                 double* hcol = H + (int64_t)j * (m + 1);
                 // v_j = w / (beta or h_{j,j-1}), V_j = Q(v_j), w = A v_j; its
@@ -388,6 +451,11 @@ static int solve_impl(const cb_csr& A, const double* b, double* x, int m, double
                 ef.mode = EPI_REORTH_FINISH;
                 ef.j = j;
                 launch_subtract(fmt, V, j + 1, nullptr, u, wc, part, reorth, -1, ef, s);
+                // stay kStepsAhead steps ahead of the GPU; stop once the cycle
+                // has ended (later steps would only check their guards)
+                if (prog_h && j + 1 < m && j >= kStepsAhead &&
+                    wait_progress(prog_h, j + 1 - kStepsAhead, s))
+                    break;
             }
             k_backsolve<<<1, 256, 0, s>>>(st, H, g, y, m, cbytes);
             if (dinv) {

@@ -91,7 +91,10 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int k = k0[u] + li + e * LPR;
-                const int kk = k < k1[u] ? k : 0;  // a real entry, or entry 0 (dropped below)
+                // a real entry, or (dropped below) the entry before the row's
+                // end: an address the row's own loads bring in anyway, not one
+                // that every lane of the launch would hit
+                const int kk = k < k1[u] ? k : max(k1[u] - 1, 0);
                 c[u][e] = ci[kk];
                 v[u][e] = val[kk];
             }
@@ -172,7 +175,7 @@ __device__ __forceinline__ void spmv_win_block(int n, int r0, const int* __restr
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int k = k0[u] + li + e * LPR;
-                const int kk = k < k1[u] ? k : 0;
+                const int kk = k < k1[u] ? k : max(k1[u] - 1, 0);  // as in spmv_rows
                 c[u][e] = ci[kk];
                 v[u][e] = val[kk];
             }
