@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "cb_internal.hpp"
@@ -272,10 +273,11 @@ static bool wait_progress(const volatile int32_t* p, int target, hipStream_t s) 
     for (unsigned it = 0;; ++it) {
         if (p[1]) return true;
         if (p[0] >= target) return false;
-        if ((it & 4095u) == 4095u) {
+        if ((it & 1023u) == 1023u) {
             if (hipStreamQuery(s) != hipErrorNotReady) return p[1] != 0;
             if (now_s() - t0 > 10.0) return false;
         }
+        std::this_thread::yield();  // steps take tens of microseconds; leave the core to other solves
     }
 }
 
