@@ -161,8 +161,6 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
     double nrm = 0.0;
     for (int rg = blockIdx.x; rg < ngroups; rg += gridDim.x) {
         const int tile0 = rg * kRowsPerWG + wave * kTile;
-        double wv[8];
-        load_rows<FMT>(w, tile0, lane, V.n, wv);  // in flight with the basis loads
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -174,6 +172,8 @@ __global__ __launch_bounds__(kThreads) void k_subtract(BasisView V, int j, const
             if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
             else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
         }
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -219,8 +219,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_subtract_project(BasisView V, i
     double nrm = 0.0;
     for (int rg = blockIdx.x; rg < ngroups; rg += G) {
         const int tile0 = rg * kRowsPerWG + wave * kTile;
-        double wv[8];
-        load_rows<FMT>(w, tile0, lane, V.n, wv);  // in flight with the basis loads
         double acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = 0.0;
@@ -229,6 +227,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_subtract_project(BasisView V, i
         // projection below re-reads these columns, last first, right away
         if (full) subtract_tile<FMT, U, kFull>(V, j, hc, tile0, lane, acc);
         else subtract_tile<FMT, U, 0>(V, j, hc, tile0, lane, acc);
+        double wv[8];
+        load_rows<FMT>(w, tile0, lane, V.n, wv);
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {

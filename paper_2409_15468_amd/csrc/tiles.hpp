@@ -238,28 +238,25 @@ __device__ __forceinline__ void subtract_tile(const BasisView& V, int j, const d
                 t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
         }
     } else {
-        // two register sets in turn (no copy from the next set into the
-        // current, which would wait for its loads): while the U columns of one
-        // set are applied, the next U are in flight.  Loads past the last
-        // column read column j - 1 again (just read, so cached) with weight 0.
-        Tile<FMT> ta[U], tb[U];
-        auto load = [&](Tile<FMT>* t, int c) {
-            int cols[U];
+        Tile<FMT> t[U], nx[U];
+        int cols[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) cols[u] = min(c + u, j - 1);
-            load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
-        };
-        auto apply = [&](Tile<FMT>* t, int c) {
+        for (int u = 0; u < U; ++u) cols[u] = min(u, j - 1);
+        load_tiles<FMT, U, LM>(t, V, cols, tile0, lane);
+        for (int c = 0; c < j; c += U) {
+            const bool more = c + U < j;
+            if (more) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
-        };
-        load(ta, 0);
-        for (int c = 0; c < j; c += 2 * U) {
-            load(tb, c + U);
-            apply(ta, c);
-            if (c + U >= j) break;  // (uniform) the last columns were in ta
-            load(ta, c + 2 * U);
-            apply(tb, c + U);
+                for (int u = 0; u < U; ++u) cols[u] = min(c + U + u, j - 1);
+                load_tiles<FMT, U, LM>(nx, V, cols, tile0, lane);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                t[u].axpy(c + u < j ? h[c + u] : 0.0, acc);
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) t[u] = nx[u];
+            }
         }
     }
 }
