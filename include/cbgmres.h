@@ -228,7 +228,7 @@ typedef struct cb_csr {
 
 /* Workspace bytes of cb_spmv / cb_residual for a matrix of n rows and nnz
  * entries: the norm's partial sums, and for rows of more than 8 entries on
- * average the column window of every 256-row block (with it, such a SpMV
+ * average the column window of every 512-row block (with it, such a SpMV
  * stages each block's window of x in LDS instead of gathering x from memory;
  * the results are the same).  -1 on a bad size. */
 int64_t cb_spmv_workspace_bytes(int32_t n, int32_t nnz);

@@ -314,7 +314,7 @@ static int check_csr(const cb_csr* A) {
 }
 
 // cb_spmv / cb_residual workspace: the norm's partial sums, then (rows of more
-// than 8 entries on average) the column windows of the 256-row blocks.
+// than 8 entries on average) the column windows of the 512-row blocks.
 static int64_t spmv_partials_bytes(const cb_csr* A) { return (8 * (int64_t)spmv_groups(A->n, A->nnz) + 255) & ~int64_t(255); }
 
 int64_t cb_spmv_workspace_bytes(int32_t n, int32_t nnz) {

@@ -171,7 +171,7 @@ void launch_reduce(const double* partials, int G, int ncols, double* out, int op
                    const int* guard, hipStream_t s);
 // y = A x (mode 0) or y = b - A x (mode 1); with partials != NULL also
 // ||y||^2 per workgroup (spmv_groups of them, summed by the consumer).
-// plan (optional, from launch_spmv_plan): per 256-row block the range of
+// plan (optional, from launch_spmv_plan): per 512-row block the range of
 // columns, so that rows longer than 8 entries on average gather x from LDS.
 void launch_spmv(const cb_csr& A, const double* x, const double* b, double* y, double* partials,
                  int mode, const int* guard, hipStream_t s, const void* plan = nullptr);

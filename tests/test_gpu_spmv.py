@@ -3,7 +3,7 @@ row lengths that select every scheme (the staged short-row scheme with its
 long-block fallback, and the lanes-per-row widths: empty rows, stencils,
 27-entry banded rows, long rows), plus the fused squared norm.  Rows of more
 than 8 entries on average run with and without the column-window plan (x
-staged in LDS per 256-row block when the block's window fits, else gathered):
+staged in LDS per 512-row block when the block's window fits, else gathered):
 y must be bit-identical either way (each row's sum is formed the same way)."""
 import numpy as np
 import pytest
