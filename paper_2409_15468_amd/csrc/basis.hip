@@ -4,9 +4,12 @@
 //
 // Row partition: workgroup g of the row kernels owns rows
 // [2048 g, 2048 (g+1)) -- 64 FRSZ2 blocks -- and thread t of it the 8 rows
-// from 2048 g + 8 t.  The partition depends on n only, so every reduction
+// from 2048 g + 8 t.  The partition depends on n only (and, for the fused
+// update + projection, on the device's resident capacity), so every reduction
 // (per-thread chain, then a fixed shuffle tree, then the 4 waves in order,
 // then the workgroups in order) is the same on every run and for every caller.
+#include <atomic>
+
 #include "cb_internal.hpp"
 #include "codec.hpp"
 #include "epilogue.hpp"
@@ -376,10 +379,36 @@ void launch_subtract(int fmt, const cb_basis& V, int j, const int* jdev, const d
                                                                 guard, ee)));
 }
 
+// Workgroups of `kernel` the current device holds at once (its occupancy per
+// CU times the CU count), cached per device and kernel format; 0 if the
+// runtime cannot say.
+static int resident_groups(const void* kernel, int fmt) {
+    constexpr int kDevs = 16, kFmts = 16;
+    static std::atomic<int> cache[kDevs][kFmts];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs || fmt < 0 || fmt >= kFmts) return 0;
+    int r = cache[dev][fmt].load(std::memory_order_relaxed);
+    if (r > 0) return r;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess)
+        return 0;
+    r = cus * per_cu;
+    if (r > 0) cache[dev][fmt].store(r, std::memory_order_relaxed);
+    return r;
+}
+
 void launch_subtract_project(int fmt, const cb_basis& V, int j, const double* h, double* w, double* partials,
                              const int* guard, const Epi& e, hipStream_t s) {
     BasisView b = view_of(V);
-    const int G = project_groups(V.n);
+    int G = project_groups(V.n);
+    // Whole waves of resident workgroups: at three per CU (the 16-bit
+    // formats), 1024 workgroups would run as 768 and then a lone 256 (measured
+    // 0.8% of an n = 2^22 inner solve); 768 that loop over the row groups do not.
+    CB_DISPATCH(fmt, ({
+        const int R = resident_groups(reinterpret_cast<const void*>(&k_subtract_project<F, 4>), F);
+        if (R > 0 && G > R) G = G / R * R;
+    }));
     dim3 grid((unsigned)G);
     Epi ee = e;
     ee.G = G;
