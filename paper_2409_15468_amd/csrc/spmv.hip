@@ -132,9 +132,10 @@ __device__ __forceinline__ double spmv_rows(int n, const int* __restrict__ rp, c
 // each block's smallest and largest column.  A block first stages its row
 // pointers and, when the block's window of x fits kWinMax doubles, that window
 // (x / d formed there once per element when DIV) in LDS with coalesced loads;
-// then each lane issues the loads of its entries for up to 8 rounds of rows at
-// once and gathers x from LDS (blocks whose window does not fit gather from
-// memory).  Scattered gathers of random columns otherwise touch a different
+// then each lane loads its entries for 4 rounds of rows at a time into one of
+// two register sets, the next set's loads in flight while the current set's
+// rows gather x from LDS and are summed (blocks whose window does not fit
+// gather from memory).  Scattered gathers of random columns otherwise touch a different
 // cache line per lane, and row pointer, entries and x each wait on the one
 // before, which bounds the SpMV far below the memory bandwidth.  Each row's
 // sum is formed exactly as in spmv_rows (same lanes, same order); the blocks
@@ -152,56 +153,76 @@ __device__ __forceinline__ void spmv_win_block(int n, int r0, const int* __restr
                                                const double* __restrict__ val, const double* __restrict__ xs,
                                                double d, const double* __restrict__ b, double* __restrict__ y,
                                                const double* xw, const int* rpl, int lo, int span, double& nrm) {
-    constexpr int RPW = 256 / LPR;               // rows per round; kWinRows / RPW rounds per block
-    constexpr int U = LPR < 8 ? LPR : 8;         // rounds whose loads are issued together
+    constexpr int RPW = 256 / LPR;                       // rows per round
+    constexpr int U = 4;                                 // rounds per register set
+    constexpr int NS = LPR * (kWinRows / 256) / U;       // sets per block
+    static_assert(NS >= 2 && NS % 2 == 0, "two register sets in turn");
     const int sub = threadIdx.x / LPR;
     const int li = threadIdx.x % LPR;
     auto gather = [&](int col) -> double {
         if (STAGED) return xw[min(max(col - lo, 0), span - 1)];  // inside the window for every real entry
         return DIV ? xs[col] / d : xs[col];
     };
-    for (int rd = 0; rd < LPR * (kWinRows / 256); rd += U) {
-        int lr[U], k0[U], k1[U];
+    struct Set {
+        int k0[U], k1[U], c[U][2];
+        double v[U][2], bq[U];
+    };
+    auto issue = [&](Set& t, int set) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            lr[u] = (rd + u) * RPW + sub;  // row within the block
-            k0[u] = rpl[lr[u]];
-            k1[u] = rpl[lr[u] + 1];
+            const int lr = (set * U + u) * RPW + sub;  // row within the block
+            t.k0[u] = rpl[lr];
+            t.k1[u] = rpl[lr + 1];
         }
-        int c[U][2];
-        double v[U][2], bq[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                const int k = k0[u] + li + e * LPR;
-                const int kk = k < k1[u] ? k : max(k1[u] - 1, 0);  // as in spmv_rows
-                c[u][e] = ci[kk];
-                v[u][e] = val[kk];
+                const int k = t.k0[u] + li + e * LPR;
+                const int kk = k < t.k1[u] ? k : max(t.k1[u] - 1, 0);  // as in spmv_rows
+                t.c[u][e] = ci[kk];
+                t.v[u][e] = val[kk];
             }
-            // b at the row, issued with the entries (a row past n reads row n - 1, unused)
-            bq[u] = b ? b[min(r0 + lr[u], n - 1)] : 0.0;
+            t.bq[u] = b ? b[min(r0 + (set * U + u) * RPW + sub, n - 1)] : 0.0;
         }
+    };
+    auto consume = [&](const Set& t, int set) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double xv[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) xv[e] = gather(c[u][e]);
+            for (int e = 0; e < 2; ++e) xv[e] = gather(t.c[u][e]);
             double s = 0.0;
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                if (k0[u] + li + e * LPR < k1[u]) s = fma(v[u][e], xv[e], s);
+                if (t.k0[u] + li + e * LPR < t.k1[u]) s = fma(t.v[u][e], xv[e], s);
             }
-            for (int k = k0[u] + li + 2 * LPR; k < k1[u]; k += LPR) s = fma(val[k], gather(ci[k]), s);
+            for (int k = t.k0[u] + li + 2 * LPR; k < t.k1[u]; k += LPR) s = fma(val[k], gather(ci[k]), s);
             s = group_sum<LPR>(s);
-            const int row = r0 + lr[u];
+            const int row = r0 + (set * U + u) * RPW + sub;
             if (row < n && li == 0) {
-                if (b) s = bq[u] - s;
+                if (b) s = t.bq[u] - s;
                 y[row] = s;
                 nrm = fma(s, s, nrm);
             }
         }
+    };
+    // two register sets in turn: while one set's rows are summed, the next
+    // set's entries are in flight.  No copy from one set into the other and no
+    // exit inside the loop, either of which would wait for every load in
+    // flight.  (8 rounds per set take 256 registers; 2 per set, or holding the
+    // residual kernel to 128, measured 1% slower per banded solve.)
+    Set A, B;
+    issue(A, 0);
+    for (int p = 0; p < NS / 2 - 1; ++p) {
+        issue(B, 2 * p + 1);
+        consume(A, 2 * p);
+        issue(A, 2 * p + 2);
+        consume(B, 2 * p + 1);
     }
+    issue(B, NS - 1);
+    consume(A, NS - 2);
+    consume(B, NS - 1);
 }
 
 template <int LPR, bool DIV>
