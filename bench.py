@@ -31,6 +31,7 @@ by probing candidates before the first restart, against every fixed format;
 Prints one JSON line.
 """
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -117,7 +118,7 @@ def timed_solves(cb, torch, A, b, x, fmt, m, tol, steps, warmup, ws):
 def event_time(torch, fn, reps):
     """Duration of fn() from HIP events recorded around each of `reps`
     launches on the current stream (the stream the library launches on), after
-    one untimed launch: (minimum, median) in seconds."""
+    one untimed launch: (mean, minimum, median) in seconds."""
     s = torch.cuda.current_stream()
     fn()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -127,7 +128,7 @@ def event_time(torch, fn, reps):
         e1.record(s)
     ev[-1][1].synchronize()
     t = sorted(e0.elapsed_time(e1) / 1e3 for e0, e1 in ev)
-    return t[0], t[len(t) // 2]
+    return sum(t) / len(t), t[0], t[len(t) // 2]
 
 
 def microbench(cb, torch, n, ncols, reps, formats):
@@ -147,31 +148,55 @@ def microbench(cb, torch, n, ncols, reps, formats):
         h = torch.empty(ncols, dtype=torch.float64, device="cuda")
         work = torch.empty(cb.cb_reduce_workspace_bytes(n, ncols + 1) // 8 + 1, dtype=torch.float64,
                            device="cuda")
-        t_dot, m_dot = event_time(torch, lambda: cb.cb_cgs_project(V, ncols, w, h, work), reps)
+        t_dot, n_dot, m_dot = event_time(torch, lambda: cb.cb_cgs_project(V, ncols, w, h, work), reps)
         wt = w.clone()
         hs = torch.full((ncols,), 1e-3, dtype=torch.float64, device="cuda")
         n2 = torch.empty(1, dtype=torch.float64, device="cuda")
-        t_upd, m_upd = event_time(torch, lambda: cb.cb_cgs_subtract(V, ncols, hs, wt, n2, work), reps)
+        t_upd, n_upd, m_upd = event_time(torch, lambda: cb.cb_cgs_subtract(V, ncols, hs, wt, n2, work), reps)
         # the first update fused with the second projection (one launch; the
         # updated w feeds the next launch, which keeps the work the same)
         wf = w.clone()
         fo = torch.empty(ncols + 1, dtype=torch.float64, device="cuda")
         hz = torch.full((ncols,), 1e-9, dtype=torch.float64, device="cuda")
-        t_fus, m_fus = event_time(torch, lambda: cb.cb_cgs_subtract_project(V, ncols, hz, wf, fo, work), reps)
+        t_fus, n_fus, m_fus = event_time(torch, lambda: cb.cb_cgs_subtract_project(V, ncols, hz, wf, fo, work), reps)
         del wf
-        xo = torch.empty(n, dtype=torch.float64, device="cuda")
-        t_dec, m_dec = event_time(torch, lambda: cb.cb_basis_load(V, 7, xo), reps * 4)
-        t_enc, m_enc = event_time(torch, lambda: cb.cb_basis_store(V, 7, cols[7]), reps * 4)
+        # A different column each launch, written to one of four output
+        # vectors in turn (compress: stored from its own input vector, so V
+        # stays as it is).  Otherwise one column's codes or one input vector
+        # would stay in the 256 MB Infinity Cache from one launch to the next,
+        # and so would one output, whose writes the cache would then absorb
+        # without writing them back: the figures would not be HBM's.
+        xo = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+        rot = itertools.count()
+
+        def dec():
+            k = next(rot)
+            cb.cb_basis_load(V, k % ncols, xo[k % 4])
+
+        t_dec, n_dec, m_dec = event_time(torch, dec, reps * 4)
+        del xo
+        rot = itertools.count()
+
+        def enc():
+            c = next(rot) % ncols
+            cb.cb_basis_store(V, c, cols[c])
+
+        t_enc, n_enc, m_enc = event_time(torch, enc, reps * 4)
         dot_bytes = ncols * n * bv + 8 * n
         upd_bytes = ncols * n * bv + 16 * n  # also the fused update + projection's
         codec_bytes = (8 + bv) * n
         out[fmt] = {
             "bytes_per_value": bv,
-            "dot_s": t_dot, "dot_GBs": dot_bytes / t_dot / 1e9, "dot_median_s": m_dot,
-            "update_s": t_upd, "update_GBs": upd_bytes / t_upd / 1e9, "update_median_s": m_upd,
-            "fused_s": t_fus, "fused_GBs": upd_bytes / t_fus / 1e9, "fused_median_s": m_fus,
-            "decompress_s": t_dec, "decompress_GBs": codec_bytes / t_dec / 1e9, "decompress_median_s": m_dec,
-            "compress_s": t_enc, "compress_GBs": codec_bytes / t_enc / 1e9, "compress_median_s": m_enc,
+            # *_s: the mean over the timed launches (GB/s from it), *_min_s and
+            # *_median_s beside it
+            "dot_s": t_dot, "dot_GBs": dot_bytes / t_dot / 1e9, "dot_min_s": n_dot, "dot_median_s": m_dot,
+            "update_s": t_upd, "update_GBs": upd_bytes / t_upd / 1e9, "update_min_s": n_upd,
+            "update_median_s": m_upd,
+            "fused_s": t_fus, "fused_GBs": upd_bytes / t_fus / 1e9, "fused_min_s": n_fus, "fused_median_s": m_fus,
+            "decompress_s": t_dec, "decompress_GBs": codec_bytes / t_dec / 1e9, "decompress_min_s": n_dec,
+            "decompress_median_s": m_dec,
+            "compress_s": t_enc, "compress_GBs": codec_bytes / t_enc / 1e9, "compress_min_s": n_enc,
+            "compress_median_s": m_enc,
         }
         log(f"microbench {fmt}: dot {out[fmt]['dot_GBs']:.0f} GB/s, update {out[fmt]['update_GBs']:.0f} GB/s, "
             f"fused update+projection {out[fmt]['fused_GBs']:.0f} GB/s, "

@@ -133,17 +133,26 @@ __device__ __forceinline__ void load_rows(const double* __restrict__ w, int tile
     }
 }
 
-template <int FMT>
+// NT: non-temporal 16-byte stores, for outputs that no later kernel of the
+// same pass reads back soon (they do not fill the caches with dirty lines).
+template <int FMT, bool NT = false>
 __device__ __forceinline__ void store_rows(double* __restrict__ w, int tile0, int lane, int n,
                                            const double* wv) {
     using M = Map<FMT>;
+    typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int k = 0; k < M::NG; ++k) {
         const int r = tile0 + M::group_row(lane, k);
         if (r + M::GS <= n) {
 #pragma unroll
-            for (int p = 0; p < M::GS; p += 2)
-                *reinterpret_cast<double2*>(w + r + p) = make_double2(wv[k * M::GS + p], wv[k * M::GS + p + 1]);
+            for (int p = 0; p < M::GS; p += 2) {
+                if constexpr (NT) {
+                    const d2v v = {wv[k * M::GS + p], wv[k * M::GS + p + 1]};
+                    __builtin_nontemporal_store(v, reinterpret_cast<d2v*>(w + r + p));
+                } else {
+                    *reinterpret_cast<double2*>(w + r + p) = make_double2(wv[k * M::GS + p], wv[k * M::GS + p + 1]);
+                }
+            }
         } else {
 #pragma unroll
             for (int p = 0; p < M::GS; ++p)
@@ -159,12 +168,12 @@ __device__ __forceinline__ void store_rows(double* __restrict__ w, int tile0, in
 // instruction scatters 16-byte pieces 32 or 64 bytes apart over 2 or 4 KB,
 // which costs the memory pipeline 2-4 times as many cache-line visits per
 // byte stored.  Whole waves call it; only this wave touches `lds`.
-template <int FMT>
+template <int FMT, bool NT = false>
 __device__ __forceinline__ void store_rows_lds(double* __restrict__ w, int tile0, int lane, int n,
                                                const double* wv, double* lds) {
     using M = Map<FMT>;
     if constexpr (M::GS == 2) {
-        store_rows<FMT>(w, tile0, lane, n, wv);
+        store_rows<FMT, NT>(w, tile0, lane, n, wv);
     } else {
 #pragma unroll
         for (int k = 0; k < M::NG; ++k) {
@@ -183,7 +192,7 @@ __device__ __forceinline__ void store_rows_lds(double* __restrict__ w, int tile0
             out[2 * k + 1] = t.y;
         }
         __builtin_amdgcn_wave_barrier();
-        store_rows<CB_F64>(w, tile0, lane, n, out);
+        store_rows<CB_F64, NT>(w, tile0, lane, n, out);
     }
 }
 
