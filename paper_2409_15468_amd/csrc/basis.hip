@@ -22,6 +22,10 @@ using namespace dev;
 
 // ----------------------------------------------------------------- store (encode)
 // Workgroup g, wave w encodes the 512-row tile starting at 2048 g + 512 w.
+// The codes go out with non-temporal stores: over launches that encode
+// different columns they sustain 2-3% more.  (Of the solver's columns only
+// each cycle's first is stored here; the steps' columns are encoded by the
+// store + SpMV kernel with ordinary stores, as the next kernel reads them.)
 template <int FMT>
 __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ values,
                                                     uint32_t* __restrict__ exps, int n, int np,
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(kThreads) void k_store(unsigned char* __restrict__ 
     }
     __shared__ double stage[kThreads / 64][kTile];
     if (v_out) store_rows_lds<FMT>(v_out, tile0, lane, n, v, stage[threadIdx.x >> 6]);
-    const bool bad = encode_tile<FMT>(values, exps, np, tile0, lane, v, bits, bs_log);
+    const bool bad = encode_tile<FMT, true>(values, exps, np, tile0, lane, v, bits, bs_log);
     if (flag && bad) atomicOr(flag, 1);
 }
 

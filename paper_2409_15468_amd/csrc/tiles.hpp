@@ -12,6 +12,21 @@
 namespace cb {
 namespace dev {
 
+// 16-byte stores of encoded data; NT: non-temporal, for a column that no
+// kernel of the same pass reads back soon.  (The 4-byte stores of frsz2_21,
+// the generic widths and the exponents stay ordinary: non-temporal, the
+// partial lines they write cost frsz2_21's encoding 10%.)
+template <bool NT>
+__device__ __forceinline__ void put16(unsigned char* p, uint4 o) {
+    if constexpr (NT) {
+        typedef unsigned u4v __attribute__((ext_vector_type(4)));
+        const u4v x = {o.x, o.y, o.z, o.w};
+        __builtin_nontemporal_store(x, reinterpret_cast<u4v*>(p));
+    } else {
+        *reinterpret_cast<uint4*>(p) = o;
+    }
+}
+
 // Encode the lane's 8 values v (rows of Map<FMT>) of the tile at row tile0
 // into one column: values at `values`, FRSZ2 block exponents at `exps`
 // (Section IV-A for frsz2; round-to-nearest-even casts for float32 and
@@ -19,8 +34,8 @@ namespace dev {
 // written.  Returns true if a stored value is not finite (for frsz2: a block
 // whose exponent field is 2047).
 // bits, bs_log: l and log2 of the block size of the generic FRSZ2 formats
-// (ignored by the others).
-template <int FMT>
+// (ignored by the others).  NT: the 16-byte value stores are non-temporal.
+template <int FMT, bool NT = false>
 __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, uint32_t* __restrict__ exps,
                                             int np, int tile0, int lane, const double* v, int bits = 0,
                                             int bs_log = 5) {
@@ -54,7 +69,7 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
                 o = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
             }
             constexpr int esz = FMT == CB_F64 ? 8 : FMT == CB_F32 ? 4 : 2;
-            if (r < np) *reinterpret_cast<uint4*>(values + (int64_t)r * esz) = o;
+            if (r < np) put16<NT>(values + (int64_t)r * esz, o);
         }
     } else if constexpr (FMT == CB_FRSZ2_32 || FMT == CB_FRSZ2_32_B64) {
         // groups of 4 values; the 8 lanes 8u..8u+7 hold one block of 32 (the
@@ -69,7 +84,7 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
             uint4 o = make_uint4(frsz2_code<32>(v[4 * k], E), frsz2_code<32>(v[4 * k + 1], E),
                                  frsz2_code<32>(v[4 * k + 2], E), frsz2_code<32>(v[4 * k + 3], E));
             if (r < np) {
-                *reinterpret_cast<uint4*>(values + (int64_t)r * 4) = o;
+                put16<NT>(values + (int64_t)r * 4, o);
                 if ((lane & ((1 << (LB - 2)) - 1)) == 0) exps[r >> LB] = E;
             }
             bad |= E == 0x7FFu;
@@ -128,8 +143,8 @@ __device__ __forceinline__ bool encode_tile(unsigned char* __restrict__ values, 
 #pragma unroll
             for (int q = 0; q < 8; ++q) c[q] = frsz2_code<16>(v[q], E);
             if (r < np) {
-                *reinterpret_cast<uint4*>(values + (int64_t)r * 2) =
-                    make_uint4(c[0] | c[1] << 16, c[2] | c[3] << 16, c[4] | c[5] << 16, c[6] | c[7] << 16);
+                put16<NT>(values + (int64_t)r * 2,
+                          make_uint4(c[0] | c[1] << 16, c[2] | c[3] << 16, c[4] | c[5] << 16, c[6] | c[7] << 16));
                 if (first) exps[r >> lb] = E;
             }
         } else {
