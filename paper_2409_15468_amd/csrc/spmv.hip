@@ -183,6 +183,7 @@ __device__ __forceinline__ void spmv_win_block(int n, int r0, const int* __restr
                 t.c[u][e] = ci[kk];
                 t.v[u][e] = val[kk];
             }
+            // b at the row, issued with the entries (a row past n reads row n - 1, unused)
             t.bq[u] = b ? b[min(r0 + (set * U + u) * RPW + sub, n - 1)] : 0.0;
         }
     };
