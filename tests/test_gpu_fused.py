@@ -10,8 +10,9 @@ oracle, fed the same stored basis, h and w (lockstep at the kernel level):
 * ||w'||^2 within 1e-13.
 
 Cases cover every kernel format (float64 and the generic widths use the
-narrow projection path), single and many column groups, ragged tails and row
-counts below and above one 2048-row group per workgroup."""
+narrow projection path), single and many column groups, ragged tails, row
+counts below and above one 2048-row group per workgroup, and launches whose
+grid is rounded down to whole rounds of resident workgroups."""
 import numpy as np
 import pytest
 
@@ -66,6 +67,16 @@ def check(fmt, n, j, seed):
                                  (2048 * 50 + 5, 60), (2048 * 36 + 31, 101), (2048 * 33 + 7, 105)])
 def test_fused_update_projection(fmt, n, j):
     check(fmt, n, j, seed=n + j)
+
+
+@pytest.mark.parametrize("fmt", ["frsz2_16", "float16", "frsz2b64_16", "frsz2_32"])
+def test_fused_update_projection_whole_rounds(fmt):
+    """Above 2^21 rows there are more row groups than workgroups (at most
+    1024), and the grid is rounded down to whole rounds of the workgroups the
+    GPU holds at once: 768 for the 16-bit formats (three per CU), so each
+    workgroup loops over one or two row groups and the last one is ragged;
+    frsz2_32 (two per CU) keeps 1024."""
+    check(fmt, 2048 * 1100 + 37, 5, seed=11)
 
 
 def test_fused_matches_separate_update_and_projection():
