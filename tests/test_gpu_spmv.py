@@ -54,6 +54,9 @@ MATRICES = {
     "skewed": lambda: skewed(3001, 4),
     "banded50k": lambda: synth.banded_random(n=50000, half_band=1000, seed=7).A,
     "wide20": lambda: random_rows(20000, 20.0, 6),  # windows wider than the LDS stage: gathers
+    "mid12": lambda: random_rows(2500, 12.0, 8),  # 8 lanes per row
+    "mid45": lambda: random_rows(2600, 45.0, 9),  # 32 lanes per row
+    "wide45": lambda: random_rows(9000, 45.0, 10),  # 32 lanes per row, gathers
 }
 
 
